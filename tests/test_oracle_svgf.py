@@ -1,0 +1,286 @@
+"""Pins of the oracle's modified SVGF (no GPU).
+
+Section 3.3 of the paper: temporal accumulation by an exponential moving
+average over back-projected history, rejection of inconsistent history,
+variance from moments or (without history) from a larger spatial kernel, and
+an iterated edge-aware spatial kernel driven by that variance.
+
+* T7  a constant image is left unchanged by the a-trous levels;
+* T8  with all edge-stopping weights equal to one every level is a normalised
+      dilated B3 convolution (scipy.ndimage.convolve);
+* T9  with a static camera the first frames after a reset are the exact
+      running mean (the 1/h ramp of the moving average);
+* T10 an integer-pixel motion shifts the history exactly; disocclusion,
+      normal, plane-distance and id rejection reset it;
+* variance from moments is the sample variance of the accumulated samples;
+  the spatial fallback on a flat patch is the variance of the pooled moments;
+* T13 the adjoint agrees with a forward-mode (dual number) JVP in the
+      dot-product test and with central differences.
+"""
+import numpy as np
+import pytest
+from scipy import ndimage
+
+H1 = np.array([1, 4, 6, 4, 1]) / 16.0
+
+
+def _geom(W, H, seed, z_const=None, cone=0.3, invalid_frac=0.0):
+    rng = np.random.default_rng(seed)
+    n = np.column_stack([rng.normal(scale=cone, size=(W * H, 2)), np.ones(W * H)])
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    z = np.full(W * H, z_const) if z_const is not None else rng.uniform(2.0, 3.0, W * H)
+    nz = np.column_stack([n, z]).astype(np.float32)
+    if invalid_frac:
+        nz[rng.random(W * H) < invalid_frac] = 0.0
+    dz = rng.normal(scale=0.05, size=(W * H, 2)).astype(np.float32)
+    return nz, dz
+
+
+# ---------------------------------------------------------------- a-trous pins
+
+def test_constant_image_unchanged(orc):
+    W, H = 37, 29
+    nz, dz = _geom(W, H, 1, invalid_frac=0.1)
+    rng = np.random.default_rng(2)
+    cv = np.column_stack([np.full(W * H, 0.37), rng.uniform(0, 0.2, W * H)])
+    P = orc.svgf_params(levels=5)
+    out = orc.svgf_spatial(P, W, H, cv, nz, dz)
+    valid = nz[:, 3] > 0
+    np.testing.assert_allclose(out[valid], 0.37, atol=1e-12)
+    assert (out[~valid] == 1.0).all()
+
+
+def test_unit_weights_reduce_to_normalised_convolution(orc):
+    W, H = 45, 38
+    nz, dz = _geom(W, H, 3, z_const=2.0, cone=0.2, invalid_frac=0.15)
+    rng = np.random.default_rng(4)
+    cv = np.column_stack([rng.random(W * H), rng.uniform(0.01, 0.3, W * H)])
+    L = 4
+    P = orc.svgf_params(levels=L, sigma_z=1.0, sigma_n=0.0, sigma_l=1e300, fp32=False)
+    valid = (nz[:, 3] > 0).reshape(H, W)
+    m = valid.astype(np.float64)
+    c = cv[:, 0].reshape(H, W).copy()
+    v = cv[:, 1].reshape(H, W).copy()
+    cur = cv.copy()
+    for level in range(L):
+        s = 1 << level
+        K = np.zeros((4 * s + 1, 4 * s + 1))
+        K[::s, ::s] = np.outer(H1, H1)
+        den = ndimage.convolve(m, K, mode="constant")
+        c_ref = ndimage.convolve(c * m, K, mode="constant") / den
+        v_ref = ndimage.convolve(v * m, K * K, mode="constant") / den ** 2
+        nxt = orc.svgf_atrous(P, W, H, level, cur, nz, dz)
+        np.testing.assert_allclose(nxt[:, 0].reshape(H, W)[valid], c_ref[valid], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(nxt[:, 1].reshape(H, W)[valid], v_ref[valid], rtol=1e-12, atol=1e-14)
+        c, v, cur = c_ref, v_ref, nxt
+
+
+def test_edge_stopping_blocks_across_depth_edge(orc):
+    # two flat regions at very different depths: no leakage across the edge
+    W, H = 32, 16
+    nz = np.tile(np.array([0, 0, 1, 2.0], np.float32), (W * H, 1))
+    nz.reshape(H, W, 4)[:, W // 2:, 3] = 20.0
+    dz = np.zeros((W * H, 2), np.float32)
+    cv = np.zeros((W * H, 2))
+    cv.reshape(H, W, 2)[:, W // 2:, 0] = 1.0
+    cv[:, 1] = 0.01
+    out = orc.svgf_spatial(orc.svgf_params(levels=5), W, H, cv, nz, dz).reshape(H, W)
+    assert out[:, : W // 2].max() < 1e-12 and out[:, W // 2:].min() > 1 - 1e-12
+
+
+# --------------------------------------------------------------- temporal pins
+
+def _plane_frame(W, H, z=5.0, oid=1):
+    pos = np.zeros((W * H, 4), np.float32)
+    yy, xx = np.divmod(np.arange(W * H), W)
+    pos[:, 0] = xx * 0.01
+    pos[:, 1] = yy * 0.01
+    pos[:, 3] = np.array([oid], np.uint32).view(np.float32)[0]
+    nz = np.tile(np.array([0, 0, 1, z], np.float32), (W * H, 1))
+    return pos, nz
+
+
+def test_static_camera_running_mean(orc):
+    W, H, n_ao = 12, 10, 8
+    pos, nz = _plane_frame(W, H)
+    mv = np.zeros((W * H, 2), np.float32)
+    P = orc.svgf_params()
+    rng = np.random.default_rng(5)
+    samples = rng.integers(0, n_ao + 1, size=(9, W * H)).astype(np.uint8)
+    hist = None
+    xs_hist = []
+    for f in range(9):
+        h = orc.svgf_temporal(P, W, H, n_ao, samples[f], pos, nz, mv, pos, nz, hist, 0.001)
+        xs = samples[f] / n_ao
+        xs_hist.append(xs)
+        X = np.array(xs_hist)
+        if f < 5:
+            # a = max(0.2, 1/h) = 1/h for h <= 5: exact running mean of values and of squares
+            np.testing.assert_allclose(h[:, 0], X.mean(0), atol=2e-6)
+            np.testing.assert_allclose(h[:, 1], X.mean(0), atol=2e-6)
+            np.testing.assert_allclose(h[:, 2], (X ** 2).mean(0), atol=2e-6)
+        if f == 3:
+            # four frames of history: variance from moments is the sample variance
+            cv = orc.svgf_variance(P, W, H, h, nz, np.zeros((W * H, 2), np.float32))
+            np.testing.assert_allclose(cv[:, 1], X.var(0), atol=4e-6)
+        np.testing.assert_array_equal(h[:, 3], min(f + 1, 255))
+        hist = h.astype(np.float32)
+    # after the ramp the weight of a new sample stays at alpha = 0.2
+    prev = hist[:, 0].astype(np.float64)
+    h = orc.svgf_temporal(P, W, H, n_ao, samples[0], pos, nz, mv, pos, nz, hist, 0.001)
+    np.testing.assert_allclose(h[:, 0], prev + 0.2 * (samples[0] / n_ao - prev), atol=1e-6)
+
+
+def test_integer_shift_moves_history_exactly(orc):
+    W, H, n_ao = 16, 8, 4
+    pos, nz = _plane_frame(W, H)
+    rng = np.random.default_rng(6)
+    c = rng.random(W * H)
+    hist_in = np.column_stack([c, c, c * c + 0.01, rng.integers(1, 9, W * H)]).astype(np.float32)
+    ao = rng.integers(0, n_ao + 1, W * H).astype(np.uint8)
+    P = orc.svgf_params()
+    # previous frame: the world point of pixel x was at pixel x + 2
+    prev_pos = pos.copy()
+    prev_pos.reshape(H, W, 4)[:, :, 0] -= 0.02
+    mv = np.tile(np.array([2.0, 0.0], np.float32), (W * H, 1))
+    out = orc.svgf_temporal(P, W, H, n_ao, ao, pos, nz, mv, prev_pos, nz, hist_in, 0.001).reshape(H, W, 4)
+    # reference: zero motion against the history rolled by two pixels
+    shifted = np.roll(hist_in.reshape(H, W, 4), -2, axis=1).reshape(-1, 4)
+    ref = orc.svgf_temporal(P, W, H, n_ao, ao, pos, nz, np.zeros_like(mv), pos, nz, shifted, 0.001).reshape(H, W, 4)
+    np.testing.assert_array_equal(out[:, : W - 2], ref[:, : W - 2])
+    # the last two columns map outside the image: disocclusion resets
+    xs = (ao.reshape(H, W) / n_ao)[:, W - 2:]
+    np.testing.assert_array_equal(out[:, W - 2:, 3], 1.0)
+    np.testing.assert_array_equal(out[:, W - 2:, 0], xs)
+    np.testing.assert_array_equal(out[:, W - 2:, 2], xs * xs)
+
+
+@pytest.mark.parametrize("case", ["id", "normal30", "normal20", "plane5", "plane3", "nan", "nohist", "prev_invalid"])
+def test_history_rejection(orc, case):
+    W, H, n_ao = 6, 5, 4
+    z, pix = 5.0, 0.002
+    pos, nz = _plane_frame(W, H, z=z)
+    prev_pos, prev_nz = pos.copy(), nz.copy()
+    hist_in = np.tile(np.array([0.5, 0.5, 0.3, 6], np.float32), (W * H, 1))
+    mv = np.zeros((W * H, 2), np.float32)
+    ao = np.full(W * H, 1, np.uint8)
+    accept = True
+    if case == "id":
+        prev_pos[:, 3] = np.array([7], np.uint32).view(np.float32)[0]
+        accept = False
+    elif case.startswith("normal"):
+        a = np.radians(30.0 if case == "normal30" else 20.0)
+        prev_nz[:, :3] = [np.sin(a), 0.0, np.cos(a)]
+        accept = case == "normal20"          # cos 20 = 0.94 >= 0.9 > cos 30 = 0.87
+    elif case.startswith("plane"):
+        k = 5.0 if case == "plane5" else 3.0
+        prev_pos[:, 2] += k * z * pix       # along the normal, k pixel footprints
+        accept = case == "plane3"
+    elif case == "nan":
+        mv[:] = np.nan
+        accept = False
+    elif case == "nohist":
+        hist_in = None
+        accept = False
+    elif case == "prev_invalid":
+        prev_nz[:, 3] = 0.0
+        accept = False
+    out = orc.svgf_temporal(orc.svgf_params(), W, H, n_ao, ao, pos, nz, mv, prev_pos, prev_nz, hist_in, pix)
+    if accept:
+        np.testing.assert_array_equal(out[:, 3], 7.0)
+        np.testing.assert_allclose(out[:, 0], 0.5 + 0.2 * (0.25 - 0.5))
+    else:
+        np.testing.assert_array_equal(out[:, 3], 1.0)
+        np.testing.assert_array_equal(out[:, 0], 0.25)
+
+
+def test_fallback_variance_is_pooled_moment_variance(orc):
+    W, H = 15, 11
+    pos, nz = _plane_frame(W, H)
+    dz = np.zeros((W * H, 2), np.float32)
+    rng = np.random.default_rng(8)
+    m1 = rng.random(W * H)
+    m2 = m1 ** 2 + rng.uniform(0, 0.05, W * H)
+    hist = np.column_stack([m1, m1, m2, np.full(W * H, 2.0)])
+    nz[rng.random(W * H) < 0.1] = 0.0            # some invalid pixels are skipped
+    P = orc.svgf_params()
+    cv = orc.svgf_variance(P, W, H, hist, nz, dz)
+    valid = (nz[:, 3] > 0).reshape(H, W)
+    M1 = m1.reshape(H, W)
+    M2 = m2.reshape(H, W)
+    for y in range(H):
+        for x in range(W):
+            if not valid[y, x]:
+                continue
+            sl = (slice(max(y - 3, 0), y + 4), slice(max(x - 3, 0), x + 4))
+            msk = valid[sl]
+            ref = M2[sl][msk].mean() - M1[sl][msk].mean() ** 2
+            assert abs(cv[y * W + x, 1] - ref) < 1e-12
+    np.testing.assert_array_equal(cv[valid.ravel(), 0], m1[valid.ravel()])
+
+
+# ------------------------------------------------------------------ adjoint pins
+
+def _vjp_case(W, H, L, seed):
+    rng = np.random.default_rng(seed)
+    nz, dz = _geom(W, H, seed, invalid_frac=0.05)
+    cv = np.column_stack([rng.random(W * H), rng.uniform(0.002, 0.05, W * H)])
+    P = orc_params(L, rng)
+    return nz, dz, cv, P
+
+
+def orc_params(L, rng):
+    import oracle
+    return oracle.svgf_params(levels=L, sigma_z=rng.uniform(0.5, 2, L), sigma_n=rng.uniform(16, 128, L),
+                              sigma_l=rng.uniform(1, 8, L), fp32=False)
+
+
+@pytest.mark.parametrize("W,H,L,seed", [(20, 16, 3, 1), (40, 36, 5, 2)])
+def test_adjoint_dot_product(orc, W, H, L, seed):
+    nz, dz, cv, P = _vjp_case(W, H, L, seed)
+    rng = np.random.default_rng(seed + 100)
+    v = rng.normal(size=W * H)
+    dcv = rng.normal(size=(W * H, 2))
+    ds = rng.normal(size=3 * L)
+    Ju = orc.svgf_spatial_jvp(P, W, H, cv, nz, dz, dcv, ds)
+    gcv, gs = orc.svgf_spatial_vjp(P, W, H, cv, nz, dz, v)
+    lhs = Ju @ v
+    rhs = (dcv * gcv).sum() + (ds * gs.ravel()).sum()
+    assert abs(lhs - rhs) <= 1e-10 * (abs(lhs) + 1e-3), (lhs, rhs)
+    # each input family alone (catches compensating errors)
+    for mask in ((1, 0, 0), (0, 1, 0), (0, 0, 1)):
+        d2 = dcv * np.array(mask[:2], float)
+        s2 = ds * mask[2]
+        lhs = orc.svgf_spatial_jvp(P, W, H, cv, nz, dz, d2, s2) @ v
+        rhs = (d2 * gcv).sum() + (s2 * gs.ravel()).sum()
+        assert abs(lhs - rhs) <= 1e-10 * (abs(lhs) + 1e-3), (mask, lhs, rhs)
+
+
+def test_adjoint_central_differences(orc):
+    W, H, L = 24, 20, 4
+    nz, dz, cv, P = _vjp_case(W, H, L, 7)
+    rng = np.random.default_rng(11)
+    g = rng.normal(size=W * H)
+    gcv, gs = orc.svgf_spatial_vjp(P, W, H, cv, nz, dz, g)
+
+    def loss(cv_, P_):
+        return orc.svgf_spatial(P_, W, H, cv_, nz, dz) @ g
+
+    for k in range(3):
+        e = rng.normal(size=(W * H, 2))
+        h = 1e-6
+        fd = (loss(cv + h * e, P) - loss(cv - h * e, P)) / (2 * h)
+        an = (e * gcv).sum()
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+    import ctypes
+    for fam, name in enumerate(("sigma_z", "sigma_n", "sigma_l")):
+        for l in range(L):
+            base = getattr(P, name)[l]
+            h = 1e-6 * max(1.0, abs(base))
+            Pp, Pm = type(P)(), type(P)()
+            ctypes.pointer(Pp)[0] = P
+            ctypes.pointer(Pm)[0] = P
+            getattr(Pp, name)[l] = base + h
+            getattr(Pm, name)[l] = base - h
+            fd = (loss(cv, Pp) - loss(cv, Pm)) / (2 * h)
+            assert abs(fd - gs[fam, l]) <= 1e-6 * max(1.0, abs(gs[fam, l])), (name, l, fd, gs[fam, l])
