@@ -1,0 +1,227 @@
+"""Benchmark of the DHR+S server hot path on one MI355X.
+
+One step = one frame of the 1920x1080 terrain workload through the whole
+path: G-buffer of primary rays, 1 AO + 2 soft-shadow rays per pixel through
+the BVH, and the modified SVGF (temporal, variance, 5 a-trous levels), with
+history and the previous G-buffer resident in HBM between frames.
+
+Prints one JSON line.  `value` is AO+shadow Mrays/s of the whole step (rays
+traced per second of step time); per-pass rates, the roofline of the dominant
+kernel and the oracle's CPU rate ride along.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# fp32 vector peak without packed-FP32 instructions (the build disables them):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# fp32 operations per traversal step, counted from the kernel source
+FLOPS_PER_NODE = 50      # two slab tests: 12 FMA (24) + 24 min/max + 2 compares
+FLOPS_PER_TRI = 51       # Moller-Trumbore: 2 cross, 4 dot, reciprocal, 3 scalings, 7 compares/adds
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--preset", default="terrain1080")
+    ap.add_argument("--cpu-frames", type=int, default=2, help="frames of the oracle CPU baseline (0 = skip)")
+    ap.add_argument("--no-counters", action="store_true")
+    return ap.parse_args()
+
+
+def svgf_bytes_per_px(levels: int) -> int:
+    """Algorithmic bytes of the filter per pixel: each pass reads its inputs
+    and writes its outputs once (neighbourhoods from cache).
+      temporal: ao 1 + pos 16 + nz 16 + mv 8 + history taps (prev pos, prev nz,
+                hist: 48) + hist_out 16                      = 105
+      variance: hist 16 + nz 16 + (c, var) 8                 =  40
+      level l : (c, var) 8 + nz 16 + dz 8 + output 8         =  40
+                (last level writes 4 bytes; level 0 also writes hist.c: +4)"""
+    return 105 + 40 + 40 * levels - 4 + 4
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
+              "(serving shards by client, one GPU each)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2406_06963_amd import binding as B
+    from paper_2406_06963_amd import workloads as wl
+
+    dev = "cuda"
+    pr = wl.preset(args.preset)
+    W, H = pr.W, pr.H
+    HW = W * H
+    nfr = args.warmup + args.steps + 1
+    scene = wl.make_scene(pr.scene)
+    cams = wl.camera_path(pr.camera, nfr, scene)
+    lights = wl.lights_for(pr.scene)
+    ctx = B.dhr_create(0)
+    t0 = time.time()
+    bvh = B.dhr_build_bvh(ctx, scene.tris, scene.obj_id)
+    bvh_s = time.time() - t0
+    info = bvh.info()
+    P = B.svgf_params(levels=pr.levels, alpha=pr.alpha)
+
+    gb = [B.gbuffer_tensors(W, H, dev) for _ in range(2)]
+    hist = [torch.empty(HW, 4, device=dev) for _ in range(2)]
+    ao = torch.empty(HW, dtype=torch.uint8, device=dev)
+    sh = torch.empty(len(lights), HW, dtype=torch.uint8, device=dev)
+    out = torch.empty(HW, device=dev)
+    work = torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device=dev)
+
+    # one event pair per pass and timed step, all on the stream the kernels run on
+    ev = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)] for k in ("gbuf", "trace", "svgf")}
+
+    def step(f, slot=None):
+        cur, prv = gb[f % 2], gb[(f + 1) % 2]
+        rec = (lambda k, e: ev[k][slot][e].record()) if slot is not None else (lambda k, e: None)
+        rec("gbuf", 0)
+        B.dhr_gbuffer(ctx, bvh, cams[f], cams[f - 1] if f > 0 else None, W, H,
+                      cur["pos"], cur["nz"], cur["dz"], cur["mv"])
+        rec("gbuf", 1)
+        tp = B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao, ao_radius=pr.ao_radius,
+                            n_shadow=pr.n_shadow, lights=lights)
+        rec("trace", 0)
+        B.dhr_trace_visibility(ctx, bvh, tp, cur["pos"], cur["nz"], ao, sh)
+        rec("trace", 1)
+        h_in = hist[(f + 1) % 2] if f > 0 else None
+        fr = B.svgf_frame(W, H, pr.n_ao, ao, cur["pos"], cur["nz"], cur["dz"], cur["mv"],
+                          prv["pos"] if f > 0 else None, prv["nz"] if f > 0 else None, h_in,
+                          hist[f % 2], out, B.pix_angle(cams[f], H), work=work)
+        rec("svgf", 0)
+        B.dhr_svgf_filter(ctx, P, [fr])
+        rec("svgf", 1)
+
+    for f in range(args.warmup):
+        step(f)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k, f in enumerate(range(args.warmup, args.warmup + args.steps)):
+        step(f, k)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    acc = {k: sum(a.elapsed_time(b) for a, b in ev[k]) for k in ev}
+    ms_per_step = (t_end - t_start) * 1e3 / args.steps
+    per = {k: acc[k] / args.steps for k in acc}
+
+    # valid pixels of the timed frames (untimed recount)
+    valid = 0
+    for f in range(args.warmup, args.warmup + args.steps):
+        g = gb[0]
+        B.dhr_gbuffer(ctx, bvh, cams[f], cams[f - 1], W, H, g["pos"], g["nz"], g["dz"], g["mv"])
+        valid += int((g["nz"][:, 3] > 0).sum().item())
+    rays_per_step = valid / args.steps * (pr.n_ao + len(lights) * pr.n_shadow)
+
+    # traversal work (instrumented kernel variant, untimed)
+    counts = None
+    if not args.no_counters:
+        c = torch.zeros(4, dtype=torch.int64, device=dev)
+        B.dhr_set_trace_counters(ctx, c)
+        for f in range(args.warmup, args.warmup + args.steps):
+            g = gb[0]
+            B.dhr_gbuffer(ctx, bvh, cams[f], cams[f - 1], W, H, g["pos"], g["nz"], g["dz"], g["mv"])
+            tp = B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao, ao_radius=pr.ao_radius,
+                                n_shadow=pr.n_shadow, lights=lights)
+            B.dhr_trace_visibility(ctx, bvh, tp, g["pos"], g["nz"], ao, sh)
+        B.dhr_set_trace_counters(ctx, None)
+        counts = [int(v) / args.steps for v in c.cpu().tolist()]
+
+    trace_s = per["trace"] / 1e3
+    svgf_s = per["svgf"] / 1e3
+    svgf_bytes = svgf_bytes_per_px(pr.levels) * HW
+    roof_svgf = {"bound": "hbm", "achieved": svgf_bytes / svgf_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": svgf_bytes / svgf_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                 "kernel": "svgf (temporal + variance + 5 a-trous levels)",
+                 "algorithmic_bytes_per_px": svgf_bytes_per_px(pr.levels)}
+    roof_trace = None
+    if counts:
+        flops = counts[1] * FLOPS_PER_NODE + counts[3] * FLOPS_PER_TRI
+        ach = flops / trace_s / 1e12
+        roof_trace = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": ach / VALU_PEAK_TFLOPS, "traffic": None, "kernel": "trace_visibility",
+                      "traced_rays": counts[0], "node_visits": counts[1], "leaf_visits": counts[2],
+                      "tri_tests": counts[3], "flops_per_node": FLOPS_PER_NODE, "flops_per_tri": FLOPS_PER_TRI}
+    dominant = "trace" if per["trace"] >= per["svgf"] else "svgf"
+    roofline = (roof_trace if (dominant == "trace" and roof_trace) else roof_svgf)
+
+    line = {
+        "metric": "AO+shadow Mrays/s and SVGF Mpix/s at 1080p; p99 frame latency, 64 clients",
+        "value": rays_per_step / (ms_per_step / 1e3) / 1e6,
+        "unit": "Mrays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": f"{pr.name}: {W}x{H}, {pr.scene} scene ({scene.n_tris} tris), "
+                               f"{pr.n_ao} AO ray (r={pr.ao_radius}) + {pr.n_shadow} soft-shadow rays/px, "
+                               f"{pr.levels}-level SVGF", "frames": args.steps,
+                   "parallelism": "single GPU"},
+        "trace_mrays_s": rays_per_step / trace_s / 1e6,
+        "svgf_mpix_s": HW / svgf_s / 1e6,
+        "pass_ms": per,
+        "valid_frac": valid / args.steps / HW,
+        "bvh": {"nodes": info["n_nodes"], "depth": info["depth"], "build_s": bvh_s,
+                "device_mb": info["device_bytes"] / 2 ** 20},
+        "roofline": roofline,
+        "roofline_svgf": roof_svgf,
+        "roofline_trace": roof_trace,
+    }
+
+    if args.cpu_frames > 0:
+        line["cpu_baseline"] = cpu_baseline(pr, scene, cams, lights, args)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(pr, scene, cams, lights, args):
+    """The oracle as it stands, timed on the host cores over a bounded sample."""
+    import numpy as np
+
+    import oracle as orc
+    W, H = pr.W, pr.H
+    so = orc.Scene(scene.tris, scene.obj_id)
+    Po = orc.svgf_params(levels=pr.levels, alpha=pr.alpha)
+    hist = None
+    prev = None
+    rays = 0
+    t_trace = t_all = 0.0
+    f0 = args.warmup
+    for f in range(f0, f0 + args.cpu_frames):
+        ts = time.perf_counter()
+        pos, nz, dz, mv = orc.gbuffer(so, cams[f], cams[f - 1], W, H)
+        tt = time.perf_counter()
+        P = orc.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao, ao_radius=pr.ao_radius,
+                             n_shadow=pr.n_shadow, lights=lights)
+        ao, sh, _ = orc.trace(so, P, pos, nz)
+        t_trace += time.perf_counter() - tt
+        pix = np.float32(2 * math.tan(0.5 * cams[f].fov_y) / H)
+        ref = orc.svgf_filter(Po, W, H, pr.n_ao, ao, pos, nz, dz, mv, prev[0] if prev else None,
+                              prev[1] if prev else None, hist, pix)
+        t_all += time.perf_counter() - ts
+        hist = ref["hist_out"].astype(np.float32)
+        prev = (pos, nz)
+        rays += int((nz[:, 3] > 0).sum()) * (pr.n_ao + len(lights) * pr.n_shadow)
+    return {"value": rays / t_all / 1e6, "unit": "Mrays/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"{args.cpu_frames} full {W}x{H} frames of the same workload (G-buffer, rays, SVGF in FP64)",
+            "trace_only_mrays_s": rays / t_trace / 1e6}
+
+
+if __name__ == "__main__":
+    main()

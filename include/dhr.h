@@ -1,0 +1,337 @@
+/*
+ * dhr.h — C ABI of the DHR+S server hot path on MI355X (gfx950).
+ *
+ * Method: Tan, Low, Chow, Teo, Bhojan, "DHR+S: distributed hybrid rendering
+ * with realistic real-time shadows for interactive thin client metaverse and
+ * game applications" (arxiv 2406.06963).  The server traces, per pixel,
+ * ambient-occlusion rays (Section 3.2, eqs. (1)-(3)) and soft-shadow rays
+ * (Section 3.1) through a bounding-volume hierarchy (Section 3.2), and
+ * reconstructs the noisy AO with a modified spatiotemporal variance-guided
+ * filter (Section 3.3).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Pixel index i = y*W + x, row 0 at the top, pixel centres at (x+0.5, y+0.5).
+ * Per-pixel device buffers (caller-owned, 16-byte aligned):
+ *   pos   float[HW][4]  world position xyz; w holds the object id's bits
+ *                       (DHR_MISS_ID where the primary ray missed)
+ *   nz    float[HW][4]  unit geometric normal facing the viewer; w = view-space
+ *                       depth z.  A pixel is VALID iff nz.w > 0.
+ *   dz    float[HW][2]  depth of the hit triangle's plane seen through pixel
+ *                       (x+1, y) and (x, y+1), minus z (1e20 when that plane is
+ *                       not in front of the camera there)
+ *   mv    float[HW][2]  motion into the history camera in pixels: the pixel's
+ *                       world position lands at (x + 0.5 + mv.x, y + 0.5 + mv.y)
+ *   hist  float[HW][4]  SVGF history (c, mu1, mu2, history length)
+ * Every call is asynchronous on the given stream (a hipStream_t; NULL = the
+ * legacy null stream) unless stated otherwise.  No call keeps a caller pointer
+ * beyond the work it enqueues.  Calls never throw; on DHR_ERR_INVALID_ARG
+ * nothing is launched and dhr_last_error() says why.  Asynchronous device
+ * faults surface at the next call or at dhr_sync() as DHR_ERR_DEVICE.  A
+ * context is not thread-safe; distinct contexts are independent.  The library
+ * keeps no per-call scratch: every buffer a call needs is passed in, so calls
+ * on different streams of one context may overlap.
+ */
+#ifndef DHR_H
+#define DHR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dhr_status {
+    DHR_OK = 0,
+    DHR_ERR_INVALID_ARG = 1,
+    DHR_ERR_OOM = 2,
+    DHR_ERR_DEVICE = 3,
+    DHR_ERR_UNSUPPORTED = 4
+} dhr_status;
+
+typedef struct dhr_ctx dhr_ctx;
+typedef struct dhr_bvh dhr_bvh;
+typedef void* dhr_stream; /* hipStream_t */
+
+#define DHR_MAX_LIGHTS 8
+#define DHR_MAX_LEVELS 8
+#define DHR_MAX_SIDE 16384
+#define DHR_MISS_ID 0xFFFFFFFFu
+
+/* ------------------------------------------------------------------------
+ * Context
+ * ------------------------------------------------------------------------ */
+
+/* Creates a context bound to HIP device `device`.  *out receives the handle
+ * (library-owned; free with dhr_destroy).  DHR_ERR_DEVICE if the device is
+ * absent, DHR_ERR_UNSUPPORTED if it is not gfx950. */
+dhr_status dhr_create(int device, dhr_ctx** out);
+void dhr_destroy(dhr_ctx* ctx);
+/* Message of the last failing call on this context ("" if none).  The string
+ * is owned by the context and valid until its next call. */
+const char* dhr_last_error(const dhr_ctx* ctx);
+/* Waits for the stream; reports an earlier asynchronous fault as
+ * DHR_ERR_DEVICE. */
+dhr_status dhr_sync(dhr_ctx* ctx, dhr_stream stream);
+const char* dhr_version(void);
+
+/* ------------------------------------------------------------------------
+ * Bounding-volume hierarchy (Section 3.2: objects are grouped hierarchically
+ * in bounding volumes so that a ray missing a volume skips its content; short
+ * rays descend less deep).
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint32_t max_leaf;   /* triangles per leaf, 1..8 (default 4)               */
+    uint32_t max_depth;  /* 8..32 (default 32); subtrees switch to median splits
+                            so the limit holds; traversal stacks are sized by it */
+    uint32_t sah_bins;   /* binned-SAH bins, 4..64 (default 16)                */
+    uint32_t threads;    /* host build threads, 0 = hardware concurrency       */
+} dhr_bvh_opts;
+
+typedef struct {
+    uint64_t n_nodes, n_tris, device_bytes;
+    uint32_t depth, max_leaf_size;
+    double sah_cost, build_ms;
+} dhr_bvh_info;
+
+/* Builds a binned-SAH BVH over T world-space triangles and uploads it to the
+ * context's device.  SYNCHRONOUS.
+ *   tris    host float[T][3][3] (vertex, xyz), not retained
+ *   obj_id  host uint32[T] or NULL (then the triangle index is the id); the id
+ *           DHR_MISS_ID is reserved
+ *   opts    NULL = defaults
+ *   out     receives the library-owned handle; free with dhr_bvh_destroy
+ * Errors: INVALID_ARG (T == 0, T > 2^28, non-finite vertex, bad opts),
+ * OOM (device allocation failed). */
+dhr_status dhr_build_bvh(dhr_ctx* ctx, const float* tris, const uint32_t* obj_id, uint32_t T,
+                         const dhr_bvh_opts* opts, dhr_bvh** out);
+dhr_status dhr_bvh_get_info(const dhr_bvh* bvh, dhr_bvh_info* info);
+void dhr_bvh_destroy(dhr_bvh* bvh);
+
+/* ------------------------------------------------------------------------
+ * G-buffer by primary rays (Section 2.2: world-space position per pixel;
+ * Section 3.3: motion vectors in the G-buffer back-project the pixel into the
+ * previous frame).  The paper rasterises this on the client's side; here it
+ * is the closest hit of the ray through each pixel centre (ties: lowest
+ * triangle index).
+ * ------------------------------------------------------------------------ */
+
+/* Pinhole camera: fwd = normalize(target - eye), right = normalize(fwd x +y),
+ * up = right x fwd; fov_y is the vertical field of view in radians; the
+ * aspect ratio is W/H. */
+typedef struct {
+    float eye[3];
+    float target[3];
+    float fov_y;
+} dhr_camera;
+
+/* Writes pos, nz, dz, mv (layouts above) for a W x H image.  prev = NULL
+ * writes NaN motion.  Missed pixels: pos = (0,0,0,DHR_MISS_ID), nz = dz = mv
+ * = 0.  Errors: INVALID_ARG (null/misaligned buffers, W or H outside
+ * 1..16384, degenerate camera). */
+dhr_status dhr_gbuffer(dhr_ctx* ctx, const dhr_bvh* bvh, const dhr_camera* cur, const dhr_camera* prev,
+                       uint32_t W, uint32_t H, float* pos, float* nz, float* dz, float* mv,
+                       dhr_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Stochastic visibility (Section 3.1 soft shadows, Section 3.2 AO).
+ * ------------------------------------------------------------------------ */
+
+/* kind 0: directional light; vec = unit direction towards it, one_minus_cos =
+ * 1 - cos(cone half-angle) (computed by the caller, e.g. 2 sin^2(theta/2));
+ * the shadow ray is unbounded.  kind 1: sphere light; vec = centre, radius =
+ * R; the cone is the sphere's solid angle seen from the ray origin and the
+ * ray ends where it enters the sphere (the ray's length is kept, Section 3.1);
+ * points within R of the centre see the light. */
+typedef struct {
+    uint32_t kind;
+    float vec[3];
+    float one_minus_cos;
+    float radius;
+} dhr_light;
+
+/* Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key (seed,
+ * client_id) and counter (x, y, frame, stream << 16 | sample); stream 0 is AO
+ * (sample = ao_sample_offset + s), stream 1 + i is light i (sample = s).
+ * u0, u1 = (r0 >> 8) 2^-24, (r1 >> 8) 2^-24.
+ * AO ray: cosine-weighted about the normal (Malley), length ao_radius;
+ * unoccluded iff nothing is hit at 0 < t < ao_radius (eq. (3)).
+ * Shadow ray: uniform in the light's cone (solid angle); a direction with
+ * n . w <= 0 is occluded without tracing.
+ * Origin o = p + eps n, eps = eps_origin_abs if > 0, else
+ * max(1e-3 ao_radius, 2^-17 max|p_k|). */
+typedef struct {
+    uint32_t W, H, frame, client_id, seed;
+    uint32_t n_ao;             /* 0..255: rays per pixel; the count fits a byte (Section 3.2) */
+    uint32_t ao_sample_offset; /* ao_sample_offset + n_ao <= 65536 */
+    float ao_radius;           /* r > 0 when n_ao > 0 */
+    uint32_t n_shadow;         /* 0..255 rays per light per pixel */
+    uint32_t n_lights;         /* 0..8 */
+    dhr_light lights[DHR_MAX_LIGHTS];
+    float eps_origin_abs;
+} dhr_trace_params;
+
+/* Traces every pixel of a W x H G-buffer.
+ *   pos, nz          device, layouts above (invalid pixels count as fully
+ *                    visible: ao = n_ao, shadow = n_shadow)
+ *   ao_count         device uint8[HW]: N_unoccluded of eq. (3)
+ *   shadow_count     device uint8[n_lights][HW]: unoccluded shadow rays per
+ *                    light; with n_shadow = 1 the bits (light i -> bit i) form
+ *                    the paper's visibility bitmask (Fig. 1).  May be NULL
+ *                    when n_lights == 0.
+ *   debug_ray_bits   NULL, or device uint64[1 + n_lights][HW]: bit s set iff
+ *                    sample s of that stream is unoccluded (needs n <= 64)
+ * Errors: INVALID_ARG (n_ao > 255, n_shadow > 255, n_lights > 8, bad light,
+ * ao_radius <= 0 with n_ao > 0, sample range, buffers). */
+dhr_status dhr_trace_visibility(dhr_ctx* ctx, const dhr_bvh* bvh, const dhr_trace_params* params,
+                                const float* pos, const float* nz, uint8_t* ao_count,
+                                uint8_t* shadow_count, uint64_t* debug_ray_bits, dhr_stream stream);
+
+/* Ragged batches for serving: one launch per pass covers every job, each
+ * with its own scene, size, camera and buffers (a batch of one is the plain
+ * call).  Results are identical to the per-job calls. */
+typedef struct {
+    const dhr_bvh* bvh;
+    dhr_camera cur, prev;
+    uint32_t has_prev;
+    uint32_t W, H;
+    float *pos, *nz, *dz, *mv;
+} dhr_gbuffer_job;
+dhr_status dhr_gbuffer_batch(dhr_ctx* ctx, const dhr_gbuffer_job* jobs, uint32_t n_jobs, dhr_stream stream);
+
+typedef struct {
+    const dhr_bvh* bvh;
+    dhr_trace_params params;
+    const float *pos, *nz;
+    uint8_t *ao_count, *shadow_count;
+} dhr_trace_job;
+dhr_status dhr_trace_visibility_batch(dhr_ctx* ctx, const dhr_trace_job* jobs, uint32_t n_jobs,
+                                      dhr_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Modified SVGF (Section 3.3).
+ *
+ * Temporal: for a valid pixel with x_s = ao_count / n_ao, the history is read
+ * at the 2x2 pixels around (x + mv.x, y + mv.y) with bilinear weights (taps
+ * of zero weight ignored).  A tap is used iff it is in the image, was valid
+ * with history length > 0, has the same object id (use_obj_id), its normal
+ * n_q satisfies n . n_q >= cos_normal_min, and |n . (p_q - p)| <=
+ * plane_px * pix * z (these two tests are evaluated in fp32 as
+ * fmaf(a.x,b.x, fmaf(a.y,b.y, a.z*b.z)) so the decision is reproducible).
+ * With usable taps: c, mu1, mu2 are the renormalised bilinear blend, h' =
+ * min(1 + max tap length, history_cap), a = max(alpha, 1/h'), am =
+ * max(alpha_moments, 1/h'), c' = c + a (x_s - c), mu1' = mu1 + am (x_s - mu1),
+ * mu2' = mu2 + am (x_s^2 - mu2).  Otherwise a reset: h' = 1, c' = mu1' =
+ * x_s, mu2' = x_s^2.
+ * Variance: h' >= var_min_history: max(0, mu2' - mu1'^2) (one fma); else
+ * the weighted variance of the pooled moments of the (2R+1)^2 valid
+ * neighbours, R = fallback_radius, weights w_z w_n of level 0.
+ * A-trous level l (stride s = 2^l): g = sqrt of the 3x3 (1,2,1)/4 blur of
+ * the variance over valid pixels; 5x5 taps q = p + s (a, b), h = B3(a) B3(b)
+ * with B3 = (1,4,6,4,1)/16; w = 1 at the centre, else
+ *   w_z = exp(-|z_p - z_q| / (sigma_z |s (a dz.x + b dz.y)| + eps_z_rel z_p))
+ *   w_n = max(0, min(1, n_p . n_q))^sigma_n   (0 when the dot is <= 0)
+ *   w_l = exp(-|c_p - c_q| / (sigma_l g + eps_l))
+ * c' = sum h w c / sum h w, v' = sum h^2 w^2 v / (sum h w)^2 over valid
+ * in-image taps.  The output of level feedback_level becomes hist_out.c.
+ * Invalid pixels: hist_out = (1,1,1,0), out = 1, never a tap or neighbour.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint32_t levels;          /* 1..8 (5) */
+    float alpha;              /* (0.2) */
+    float alpha_moments;      /* (0.2) */
+    float sigma_z[DHR_MAX_LEVELS]; /* > 0 (1) */
+    float sigma_n[DHR_MAX_LEVELS]; /* >= 0 (128) */
+    float sigma_l[DHR_MAX_LEVELS]; /* > 0 (4) */
+    float eps_z_rel;          /* (1e-4) */
+    float eps_l;              /* (1e-4) */
+    float cos_normal_min;     /* (0.9) */
+    float plane_px;           /* (4) */
+    uint32_t use_obj_id;      /* (1) */
+    uint32_t var_min_history; /* (4) */
+    uint32_t fallback_radius; /* 0..3 (3) */
+    uint32_t feedback_level;  /* < levels (0) */
+    float history_cap;        /* >= 1 (255) */
+} dhr_svgf_params;
+
+/* Fills the defaults above. */
+void dhr_svgf_default_params(dhr_svgf_params* p);
+
+typedef struct {
+    uint32_t W, H, n_ao;        /* n_ao >= 1: the denominator of x_s */
+    const uint8_t* ao_count;    /* device uint8[HW] */
+    const float *pos, *nz, *dz, *mv;
+    const float *prev_pos, *prev_nz, *hist_in; /* previous frame; hist_in NULL = no history */
+    float* hist_out;            /* device float[HW][4]; must not alias hist_in */
+    float* out;                 /* device float[HW]: filtered AO */
+    float* save;                /* NULL or device float[levels][HW][2]: the input
+                                   (c, var) of every level, for dhr_svgf_backward */
+    float* work;                /* device scratch of dhr_svgf_workspace_bytes(W,H,p,0)
+                                   bytes; may be NULL when save is given */
+    float pix;                  /* 2 tan(fov_y / 2) / H of the current camera */
+} dhr_svgf_frame;
+
+/* Temporal -> variance -> levels for n_frames frames (a ragged batch; one
+ * launch per pass).  Errors: INVALID_ARG (bad params, n_ao == 0, buffers,
+ * hist_out aliasing hist_in). */
+dhr_status dhr_svgf_filter(dhr_ctx* ctx, const dhr_svgf_params* params, const dhr_svgf_frame* frames,
+                           uint32_t n_frames, dhr_stream stream);
+
+/* Differentiable part alone: the a-trous levels applied to given (c, var). */
+typedef struct {
+    uint32_t W, H;
+    const float* cv_in;         /* device float[HW][2] */
+    const float *nz, *dz;
+    float* out;                 /* device float[HW] */
+    float* save;                /* NULL or device float[levels][HW][2] */
+    float* work;                /* dhr_svgf_workspace_bytes(W,H,p,0) bytes, or NULL with save */
+} dhr_svgf_spatial_frame;
+dhr_status dhr_svgf_spatial_forward(dhr_ctx* ctx, const dhr_svgf_params* params,
+                                    const dhr_svgf_spatial_frame* frames, uint32_t n_frames,
+                                    dhr_stream stream);
+
+/* Vector-Jacobian product of the spatial stack (levels and variance
+ * prefilter) for a loss L of the output:
+ *   grad_out  device float[HW] = dL/d out
+ *   grad_cv   device float[HW][2] receives dL/d (c_in, var_in)
+ *   grad_sigma device float[3][levels] receives dL/d (sigma_z, sigma_n,
+ *             sigma_l), summed over all frames (overwritten; deterministic)
+ * Kinks take the subgradient 0.  No gradient flows into z, normals or the
+ * history.  work: dhr_svgf_workspace_bytes(W,H,p,1) bytes per frame. */
+typedef struct {
+    uint32_t W, H;
+    const float* save;          /* from the forward call with the same params */
+    const float *nz, *dz;
+    const float* grad_out;
+    float* grad_cv;
+    float* work;
+} dhr_svgf_bwd_frame;
+dhr_status dhr_svgf_backward(dhr_ctx* ctx, const dhr_svgf_params* params, const dhr_svgf_bwd_frame* frames,
+                             uint32_t n_frames, float* grad_sigma, dhr_stream stream);
+
+/* Scratch bytes one frame needs: which = 0 forward (filter / spatial), 1
+ * backward. */
+uint64_t dhr_svgf_workspace_bytes(uint32_t W, uint32_t H, const dhr_svgf_params* params, int which);
+
+/* Instrumentation for measurement: while `counters` (device uint64[4], or
+ * NULL to switch off) is set, trace calls on this context run a counting
+ * variant of the kernel that adds (rays traced, interior-node visits, leaf
+ * visits, triangle tests) into it.  Results are unchanged; the counting
+ * variant is slower and is never the timed one. */
+dhr_status dhr_set_trace_counters(dhr_ctx* ctx, uint64_t* counters);
+
+/* ------------------------------------------------------------------------
+ * The random-number generator alone (ray generation uses it in-kernel):
+ * n counters (device uint32[n][4]) under key (k0, k1) -> device
+ * uint32[n][4].
+ * ------------------------------------------------------------------------ */
+dhr_status dhr_philox4x32_10(dhr_ctx* ctx, uint32_t k0, uint32_t k1, const uint32_t* ctr, uint32_t* out,
+                             uint64_t n, dhr_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DHR_H */

@@ -22,6 +22,10 @@
  *   dz   float[HW][2]  depth of the hit plane at pixel +x / +y minus depth
  *   mv   float[HW][2]  motion to the history camera, in pixels
  *   hist float[HW][4]  (c, mu1, mu2, history length)
+ *
+ * The history is an fp32 buffer: the temporal step rounds its result to fp32
+ * once when it stores it (returned here as FP64 values that are exactly
+ * representable in fp32), and the variance estimate reads the stored values.
  */
 #ifndef ORC_H
 #define ORC_H

@@ -78,13 +78,17 @@ void orc_svgf_temporal(const orc_svgf_params* P, int W, int H, int n_ao, const u
             double wsum = 0.0, c = 0.0, m1 = 0.0, m2 = 0.0, hmax = 0.0;
             const float mvx = mv[2 * i], mvy = mv[2 * i + 1];
             if (have_hist && std::isfinite(mvx) && std::isfinite(mvy)) {
-                // bilinear taps around the back-projected position
+                // bilinear taps around the back-projected position.  The
+                // fraction is rounded to fp32 (the motion vector's own
+                // precision) and a tap takes part iff its bilinear factor is
+                // nonzero: tap 0 iff f < 1, tap 1 iff f > 0.
                 const double flx = std::floor((double)mvx), fly = std::floor((double)mvy);
-                const double fx = (double)mvx - flx, fy = (double)mvy - fly;
+                const double fx = (double)(float)((double)mvx - flx), fy = (double)(float)((double)mvy - fly);
                 const double X0 = x + flx, Y0 = y + fly;
                 for (int j = 0; j < 2; ++j)
                     for (int k = 0; k < 2; ++k) {
-                        if ((k == 1 && !(fx > 0.0)) || (j == 1 && !(fy > 0.0))) continue;
+                        if ((k == 1 && !(fx > 0.0)) || (k == 0 && !(fx < 1.0))) continue;
+                        if ((j == 1 && !(fy > 0.0)) || (j == 0 && !(fy < 1.0))) continue;
                         const double tx = X0 + k, ty = Y0 + j;
                         if (tx < 0.0 || tx >= W || ty < 0.0 || ty >= H) continue;
                         const int64_t q = (int64_t)ty * W + (int64_t)tx;
@@ -120,6 +124,9 @@ void orc_svgf_temporal(const orc_svgf_params* P, int W, int H, int n_ao, const u
                 ho[2] = xs * xs;
                 ho[3] = 1.0;
             }
+            // the history buffer holds fp32: the step's result is stored once,
+            // rounded to fp32, and everything downstream reads the stored value
+            for (int k = 0; k < 4; ++k) ho[k] = (double)(float)ho[k];
         }
     }
 }
@@ -204,7 +211,7 @@ void orc_svgf_filter(const orc_svgf_params* P, int W, int H, int n_ao, const uin
         std::swap(a, b);
         if (l == P->feedback_level)
             for (int64_t i = 0; i < HW; ++i)
-                if (orc::valid_px(nz, i)) hist_out[4 * i] = a[2 * i];
+                if (orc::valid_px(nz, i)) hist_out[4 * i] = (double)(float)a[2 * i];
     }
     for (int64_t i = 0; i < HW; ++i) out[i] = orc::valid_px(nz, i) ? a[2 * i] : 1.0;
 }

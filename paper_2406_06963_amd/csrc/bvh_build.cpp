@@ -1,0 +1,368 @@
+// Host BVH builder: binned surface-area heuristic (Wald, "On fast
+// construction of SAH-based bounding volume hierarchies", 2007), with the
+// tree depth capped so that device traversal stacks have a fixed size, then
+// flattened into the device layout (child boxes stored in the parent, leaves
+// as triangle ranges).  The paper relies on the driver's hierarchy
+// (Section 3.2); this is the library's own.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <future>
+#include <limits>
+#include <memory>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+
+namespace dhr {
+namespace {
+
+constexpr float kInf = std::numeric_limits<float>::infinity();
+
+struct Box {
+    float lo[3] = {kInf, kInf, kInf};
+    float hi[3] = {-kInf, -kInf, -kInf};
+    void grow(const Box& b) {
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], b.lo[k]);
+            hi[k] = std::max(hi[k], b.hi[k]);
+        }
+    }
+    void grow(const float* p) {
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], p[k]);
+            hi[k] = std::max(hi[k], p[k]);
+        }
+    }
+    double area() const {
+        double d[3];
+        for (int k = 0; k < 3; ++k) d[k] = std::max(0.0, (double)hi[k] - (double)lo[k]);
+        return 2.0 * (d[0] * d[1] + d[1] * d[2] + d[2] * d[0]);
+    }
+};
+
+struct Prim {
+    Box b;
+    float c[3];
+    uint32_t idx;
+};
+
+struct BNode {
+    Box box;
+    std::unique_ptr<BNode> kid[2];
+    uint32_t first = 0, count = 0;  // leaf when count > 0
+};
+
+uint32_t ceil_log2(uint64_t v) {
+    uint32_t r = 0;
+    while ((1ull << r) < v) ++r;
+    return r;
+}
+
+class Builder {
+   public:
+    Builder(std::vector<Prim>& prims, const dhr_bvh_opts& o) : prims_(prims), o_(o) {
+        threads_left_ = (int)(o.threads ? o.threads : std::max(1u, std::thread::hardware_concurrency())) - 1;
+    }
+
+    std::unique_ptr<BNode> build(uint32_t b, uint32_t e, uint32_t depth) {
+        auto node = std::make_unique<BNode>();
+        Box cb;
+        for (uint32_t i = b; i < e; ++i) {
+            node->box.grow(prims_[i].b);
+            cb.grow(prims_[i].c);
+        }
+        const uint32_t n = e - b;
+        if (n <= o_.max_leaf) {
+            node->first = b;
+            node->count = n;
+            return node;
+        }
+        const uint32_t need = ceil_log2((n + o_.max_leaf - 1) / o_.max_leaf);
+        uint32_t mid = 0;
+        if (depth + need < o_.max_depth) mid = sah_split(b, e, cb);
+        if (mid <= b || mid >= e) mid = median_split(b, e, cb);
+        if (n > 32768 && threads_left_.fetch_sub(1) > 0) {
+            auto fut = std::async(std::launch::async, [&, b, mid, depth] { return build(b, mid, depth + 1); });
+            node->kid[1] = build(mid, e, depth + 1);
+            node->kid[0] = fut.get();
+            threads_left_.fetch_add(1);
+        } else {
+            node->kid[0] = build(b, mid, depth + 1);
+            node->kid[1] = build(mid, e, depth + 1);
+        }
+        return node;
+    }
+
+   private:
+    // Object median on the widest centroid axis (ties broken by index).
+    uint32_t median_split(uint32_t b, uint32_t e, const Box& cb) {
+        int axis = 0;
+        float best = -1.0f;
+        for (int k = 0; k < 3; ++k)
+            if (cb.hi[k] - cb.lo[k] > best) best = cb.hi[k] - cb.lo[k], axis = k;
+        uint32_t mid = b + (e - b) / 2;
+        std::nth_element(prims_.begin() + b, prims_.begin() + mid, prims_.begin() + e,
+                         [axis](const Prim& x, const Prim& y) {
+                             return x.c[axis] < y.c[axis] || (x.c[axis] == y.c[axis] && x.idx < y.idx);
+                         });
+        return mid;
+    }
+
+    // Binned SAH: cost(split) = A_L N_L + A_R N_R over bin boundaries.
+    uint32_t sah_split(uint32_t b, uint32_t e, const Box& cb) {
+        const uint32_t K = o_.sah_bins;
+        double best_cost = std::numeric_limits<double>::infinity();
+        int best_axis = -1;
+        uint32_t best_bin = 0;
+        std::vector<Box> bins(K);
+        std::vector<uint32_t> cnt(K);
+        std::vector<double> rarea(K);
+        std::vector<uint32_t> rcnt(K);
+        for (int axis = 0; axis < 3; ++axis) {
+            const float lo = cb.lo[axis], ext = cb.hi[axis] - cb.lo[axis];
+            if (!(ext > 0.0f)) continue;
+            const float scale = (float)K / ext;
+            std::fill(bins.begin(), bins.end(), Box());
+            std::fill(cnt.begin(), cnt.end(), 0u);
+            for (uint32_t i = b; i < e; ++i) {
+                uint32_t k = std::min(K - 1, (uint32_t)((prims_[i].c[axis] - lo) * scale));
+                bins[k].grow(prims_[i].b);
+                ++cnt[k];
+            }
+            Box acc;
+            uint32_t c = 0;
+            for (int k = (int)K - 1; k > 0; --k) {
+                acc.grow(bins[k]);
+                c += cnt[k];
+                rarea[k] = acc.area();
+                rcnt[k] = c;
+            }
+            acc = Box();
+            c = 0;
+            for (uint32_t k = 0; k + 1 < K; ++k) {
+                acc.grow(bins[k]);
+                c += cnt[k];
+                if (c == 0 || rcnt[k + 1] == 0) continue;
+                double cost = acc.area() * c + rarea[k + 1] * rcnt[k + 1];
+                if (cost < best_cost) best_cost = cost, best_axis = axis, best_bin = k;
+            }
+        }
+        if (best_axis < 0) return b;  // every centroid coincides: caller takes the median
+        const float lo = cb.lo[best_axis], scale = (float)K / (cb.hi[best_axis] - cb.lo[best_axis]);
+        auto it = std::partition(prims_.begin() + b, prims_.begin() + e, [&](const Prim& p) {
+            return std::min(K - 1, (uint32_t)((p.c[best_axis] - lo) * scale)) <= best_bin;
+        });
+        return (uint32_t)(it - prims_.begin());
+    }
+
+    std::vector<Prim>& prims_;
+    const dhr_bvh_opts& o_;
+    std::atomic<int> threads_left_{0};
+};
+
+struct Flattener {
+    std::vector<float4> out;  // 4 per node
+    float pad = 0.0f;
+    uint32_t depth = 0, max_leaf = 0;
+    double sah = 0.0, root_area = 1.0;
+
+    static int leaf_ref(uint32_t first, uint32_t count) {
+        return ~(int)((first << kLeafCountBits) | (count - 1));
+    }
+
+    int ref_of(const BNode* n, uint32_t d) {
+        if (n->count > 0) {
+            depth = std::max(depth, d);
+            max_leaf = std::max(max_leaf, n->count);
+            sah += n->box.area() / root_area * n->count;
+            return leaf_ref(n->first, n->count);
+        }
+        return emit(n, d);
+    }
+
+    // Writes an internal node; returns its index.
+    int emit(const BNode* n, uint32_t d) {
+        const int id = (int)(out.size() / 4);
+        out.resize(out.size() + 4);
+        sah += n->box.area() / root_area;  // traversal step
+        const Box* kb[2];
+        Box empty;
+        empty.lo[0] = empty.lo[1] = empty.lo[2] = 1e30f;
+        empty.hi[0] = empty.hi[1] = empty.hi[2] = -1e30f;
+        int ref[2];
+        for (int k = 0; k < 2; ++k) {
+            if (n->kid[k]) {
+                kb[k] = &n->kid[k]->box;
+                ref[k] = ref_of(n->kid[k].get(), d + 1);
+            } else {
+                kb[k] = &empty;
+                ref[k] = -1;
+            }
+        }
+        float lo[2][3], hi[2][3];
+        for (int k = 0; k < 2; ++k)
+            for (int a = 0; a < 3; ++a) {
+                bool real = n->kid[k] != nullptr;
+                lo[k][a] = real ? kb[k]->lo[a] - pad : kb[k]->lo[a];
+                hi[k][a] = real ? kb[k]->hi[a] + pad : kb[k]->hi[a];
+            }
+        float4* o = &out[4 * id];
+        o[0] = make_float4(lo[0][0], hi[0][0], lo[0][1], hi[0][1]);
+        o[1] = make_float4(lo[1][0], hi[1][0], lo[1][1], hi[1][1]);
+        o[2] = make_float4(lo[0][2], hi[0][2], lo[1][2], hi[1][2]);
+        int4 r = make_int4(ref[0], ref[1], 0, 0);
+        std::memcpy(&o[3], &r, 16);
+        return id;
+    }
+};
+
+}  // namespace
+
+bool build_host_bvh(const float* tris, const uint32_t* obj_id, uint32_t T, const dhr_bvh_opts& o, HostBvh* out) {
+    std::vector<Prim> prims(T);
+    float maxabs = 0.0f;
+    for (uint32_t i = 0; i < T; ++i) {
+        Prim& p = prims[i];
+        const float* v = tris + 9ull * i;
+        for (int k = 0; k < 9; ++k) {
+            if (!std::isfinite(v[k])) {
+                out->error = "non-finite vertex coordinate in triangle " + std::to_string(i);
+                return false;
+            }
+            maxabs = std::max(maxabs, std::fabs(v[k]));
+        }
+        p.b.grow(v);
+        p.b.grow(v + 3);
+        p.b.grow(v + 6);
+        for (int k = 0; k < 3; ++k) p.c[k] = 0.5f * (p.b.lo[k] + p.b.hi[k]);
+        p.idx = i;
+    }
+    Builder builder(prims, o);
+    std::unique_ptr<BNode> root = builder.build(0, T, 0);
+
+    Flattener fl;
+    // Boxes grow outward by 2^-20 of the scene's largest coordinate so that
+    // rounding in the fp32 slab test can never reject a box that holds a hit.
+    fl.pad = std::ldexp(std::max(maxabs, 1e-6f), -20);
+    fl.root_area = std::max(root->box.area(), 1e-30);
+    if (root->count > 0) {
+        // a single leaf: wrap it in an internal root whose second child is empty
+        auto wrap = std::make_unique<BNode>();
+        wrap->box = root->box;
+        wrap->kid[0] = std::move(root);
+        root = std::move(wrap);
+    }
+    fl.emit(root.get(), 0);
+
+    out->n_nodes = fl.out.size() / 4;
+    out->depth = fl.depth;
+    out->max_leaf_size = fl.max_leaf;
+    out->sah_cost = fl.sah;
+    out->nodes = (float4*)std::malloc(fl.out.size() * sizeof(float4));
+    out->tris = (float4*)std::malloc(3ull * T * sizeof(float4));
+    if (!out->nodes || !out->tris) {
+        std::free(out->nodes);
+        std::free(out->tris);
+        out->nodes = out->tris = nullptr;
+        out->error = "host allocation failed";
+        return false;
+    }
+    std::memcpy(out->nodes, fl.out.data(), fl.out.size() * sizeof(float4));
+    for (uint32_t i = 0; i < T; ++i) {
+        const uint32_t src = prims[i].idx;
+        const float* v = tris + 9ull * src;
+        uint32_t oid = obj_id ? obj_id[src] : src;
+        float fidx, foid;
+        std::memcpy(&fidx, &src, 4);
+        std::memcpy(&foid, &oid, 4);
+        out->tris[3ull * i + 0] = make_float4(v[0], v[1], v[2], fidx);
+        out->tris[3ull * i + 1] = make_float4(v[3] - v[0], v[4] - v[1], v[5] - v[2], foid);
+        out->tris[3ull * i + 2] = make_float4(v[6] - v[0], v[7] - v[1], v[8] - v[2], 0.0f);
+    }
+    return true;
+}
+
+}  // namespace dhr
+
+extern "C" {
+
+dhr_status dhr_build_bvh(dhr_ctx* ctx, const float* tris, const uint32_t* obj_id, uint32_t T,
+                         const dhr_bvh_opts* opts, dhr_bvh** out) {
+    if (!ctx) return DHR_ERR_INVALID_ARG;
+    if (!tris || !out) return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_build_bvh: null pointer");
+    *out = nullptr;
+    if (T == 0 || T > (1u << 28))
+        return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_build_bvh: T = %u outside 1..2^28", T);
+    dhr_bvh_opts o{4, 32, 16, 0};
+    if (opts) o = *opts;
+    if (o.max_leaf == 0) o.max_leaf = 4;
+    if (o.max_depth == 0) o.max_depth = 32;
+    if (o.sah_bins == 0) o.sah_bins = 16;
+    if (o.max_leaf > 8 || o.max_depth < 8 || o.max_depth > 32 || o.sah_bins < 4 || o.sah_bins > 64)
+        return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_build_bvh: options out of range");
+    if ((uint64_t)(T + o.max_leaf - 1) / o.max_leaf > (1ull << o.max_depth))
+        return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_build_bvh: max_depth too small for T");
+    if (obj_id)
+        for (uint32_t i = 0; i < T; ++i)
+            if (obj_id[i] == DHR_MISS_ID)
+                return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_build_bvh: object id 0xFFFFFFFF is reserved");
+
+    auto t0 = std::chrono::steady_clock::now();
+    dhr::HostBvh hb;
+    if (!dhr::build_host_bvh(tris, obj_id, T, o, &hb))
+        return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_build_bvh: %s", hb.error.c_str());
+
+    dhr::DeviceGuard g(ctx->device);
+    dhr_bvh* b = new dhr_bvh;
+    b->ctx = ctx;
+    const size_t nb = hb.n_nodes * 4 * sizeof(float4), tb = 3ull * T * sizeof(float4);
+    if (hipMalloc(&b->nodes, nb) != hipSuccess || hipMalloc(&b->tris, tb) != hipSuccess) {
+        if (b->nodes) (void)hipFree(b->nodes);
+        delete b;
+        std::free(hb.nodes);
+        std::free(hb.tris);
+        (void)hipGetLastError();
+        return dhr::set_error(ctx, DHR_ERR_OOM, "dhr_build_bvh: device allocation of %zu bytes failed", nb + tb);
+    }
+    hipError_t e1 = hipMemcpy(b->nodes, hb.nodes, nb, hipMemcpyHostToDevice);
+    hipError_t e2 = hipMemcpy(b->tris, hb.tris, tb, hipMemcpyHostToDevice);
+    std::free(hb.nodes);
+    std::free(hb.tris);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        (void)hipFree(b->nodes);
+        (void)hipFree(b->tris);
+        delete b;
+        return dhr::set_error(ctx, DHR_ERR_DEVICE, "dhr_build_bvh: upload failed: %s",
+                              hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    }
+    b->info.n_nodes = hb.n_nodes;
+    b->info.n_tris = T;
+    b->info.device_bytes = nb + tb;
+    b->info.depth = hb.depth;
+    b->info.max_leaf_size = hb.max_leaf_size;
+    b->info.sah_cost = hb.sah_cost;
+    b->info.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = b;
+    return DHR_OK;
+}
+
+dhr_status dhr_bvh_get_info(const dhr_bvh* bvh, dhr_bvh_info* info) {
+    if (!bvh || !info) return DHR_ERR_INVALID_ARG;
+    *info = bvh->info;
+    return DHR_OK;
+}
+
+void dhr_bvh_destroy(dhr_bvh* bvh) {
+    if (!bvh) return;
+    dhr::DeviceGuard g(bvh->ctx->device);
+    (void)hipFree(bvh->nodes);
+    (void)hipFree(bvh->tris);
+    delete bvh;
+}
+
+}  // extern "C"

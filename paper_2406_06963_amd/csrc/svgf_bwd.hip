@@ -1,0 +1,341 @@
+// Adjoint of the spatial filter stack (the a-trous levels of Section 3.3 with
+// their variance prefilter): gradients of a loss with respect to the input AO
+// value c, the input variance v and the per-level sigma_z, sigma_n, sigma_l.
+//
+// For one level with c'_p = sum_q h w_pq c_q / D_p, v'_p = sum_q h^2 w_pq^2
+// v_q / D_p^2 and incoming adjoints (a_p, b_p) of (c'_p, v'_p), write A = a/D,
+// B = b/D^2, K = 2 B v' D.  The adjoint of a tap weight is
+//     wbar_pq = h (A_p (c_q - c'_p) - K_p) + 2 B_p h^2 w_pq v_q,
+// the direct terms are dc_q += A_p h w, dv_q += B_p h^2 w^2, and the weight
+// chain rule reaches c_p, c_q (through w_l), the prefiltered deviation g_p and
+// the sigmas.  Pass A runs per centre pixel p (coefficients, the centre-role
+// terms, g's adjoint, sigma partials); pass B runs per neighbour q and gathers
+// over p = q - s (a, b): no atomics, so results are deterministic.  Sigma
+// partials are summed per tile in FP64 and reduced in a fixed order.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "svgf_common.h"
+
+namespace dhr {
+
+dhr_status svgf_check_params(dhr_ctx* ctx, const dhr_svgf_params* p, const char* what);
+
+namespace {
+
+struct BwdDesc {
+    uint32_t W, H, tiles_x, tiles;
+    const float2* save;     // [levels][HW]
+    const float4* nz;
+    const float2* dz;
+    const float* grad_out;  // [HW]
+    float2* grad_cv;        // [HW]
+    float2* g0;             // adjoint ping-pong [HW] x 2
+    float2* g1;
+    float4* coef;           // [HW] (A, B, c', E)
+    float4* aux;            // [HW] (prefilter adjoint / sk, centre-role dc, K, 0)
+    double* part;           // [levels][tiles][3]
+};
+constexpr int kBwdMaxB = 24;
+using BwdBatch = Batch<BwdDesc, kBwdMaxB>;
+static_assert(sizeof(BwdBatch) <= 4000, "kernel arguments too large");
+
+__device__ __forceinline__ float2* adj_out(const BwdDesc& D, uint32_t l, uint32_t L) {
+    return l == 0 ? D.grad_cv : (((L - 1 - l) & 1u) ? D.g1 : D.g0);
+}
+
+__device__ __forceinline__ float sgn(float v) { return v > 0.0f ? 1.0f : (v < 0.0f ? -1.0f : 0.0f); }
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int k = 0; k < kSvgfBlock / 64; ++k) s += red[k];
+    return s;
+}
+
+__global__ __launch_bounds__(kSvgfBlock) void adjoint_a_kernel(const BwdBatch Bt, const SvgfK P, uint32_t level) {
+    __shared__ double red[kSvgfBlock / 64];
+    const int j = find_job(Bt.tile0, (int)Bt.n, blockIdx.x);
+    const BwdDesc& D = Bt.d[j];
+    const uint32_t tile = blockIdx.x - Bt.tile0[j];
+    uint32_t x, y;
+    tile_xy(tile, D.tiles_x, x, y);
+    const uint32_t L = P.levels;
+    const int W = (int)D.W, H = (int)D.H, s = 1 << level;
+    float s_z = 0.0f, s_n = 0.0f, s_l = 0.0f;
+    if (x < D.W && y < D.H) {
+        const size_t i = (size_t)y * W + x;
+        const float2* cv = D.save + (size_t)level * W * H;
+        const float4 n4 = D.nz[i];
+        if (!(n4.w > 0.0f)) {
+            D.coef[i] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+            D.aux[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        } else {
+            float ab, bb;
+            if (level + 1 == L) {
+                ab = D.grad_out[i];
+                bb = 0.0f;
+            } else {
+                const float2 g = adj_out(D, level + 1, L)[i];
+                ab = g.x;
+                bb = g.y;
+            }
+            float G = 0.0f, sk = 0.0f;
+#pragma unroll
+            for (int b = -1; b <= 1; ++b)
+#pragma unroll
+                for (int a = -1; a <= 1; ++a) {
+                    const int qx = (int)x + a, qy = (int)y + b;
+                    if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
+                    const size_t q = (size_t)qy * W + qx;
+                    if (!(D.nz[q].w > 0.0f)) continue;
+                    const float k = k3(a) * k3(b);
+                    G = fmaf(k, cv[q].y, G);
+                    sk += k;
+                }
+            const float g = sqrtf(G / sk);
+            const float sl = P.sl[level], sz = P.sz[level], sn = P.sn[level];
+            const float E = fmaf(sl, g, P.eps_l);
+            const float2 cvp = cv[i];
+            const float2 dzp = D.dz[i];
+            const float3 np = f3(n4);
+            float wv[25], cq[25], vq[25], zq[25], xn[25];
+            float Dn = 0.0f, Sc = 0.0f, Sv = 0.0f;
+#pragma unroll
+            for (int t = 0; t < 25; ++t) {
+                const int a = t % 5 - 2, b = t / 5 - 2;
+                wv[t] = -1.0f;
+                cq[t] = vq[t] = zq[t] = xn[t] = 0.0f;
+                const int qx = (int)x + s * a, qy = (int)y + s * b;
+                if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
+                const size_t q = (size_t)qy * W + qx;
+                const float4 nq = D.nz[q];
+                if (!(nq.w > 0.0f)) continue;
+                const float2 c2 = cv[q];
+                float w = 1.0f;
+                if (a != 0 || b != 0)
+                    w = w_depth(n4.w, nq.w, dzp, a, b, s, sz, P.eps_z) * w_normal(np, f3(nq), sn) *
+                        expf(-fabsf(cvp.x - c2.x) / E);
+                wv[t] = w;
+                cq[t] = c2.x;
+                vq[t] = c2.y;
+                zq[t] = nq.w;
+                xn[t] = fminf(dot3(np, f3(nq)), 1.0f);
+                const float hw = b3(a) * b3(b) * w;
+                Dn += hw;
+                Sc = fmaf(hw, c2.x - cvp.x, Sc);
+                Sv = fmaf(hw * hw, c2.y, Sv);
+            }
+            const float cpr = cvp.x + Sc / Dn, vpr = Sv / (Dn * Dn);
+            const float A = ab / Dn, Bc = bb / (Dn * Dn);
+            const float K2 = 2.0f * Bc * vpr * Dn;
+            float cbar_c = 0.0f, gbar = 0.0f;
+            const float iE2 = 1.0f / (E * E);
+#pragma unroll
+            for (int t = 0; t < 25; ++t) {
+                const int a = t % 5 - 2, b = t / 5 - 2;
+                const float w = wv[t];
+                if (w < 0.0f || (a == 0 && b == 0)) continue;
+                const float h = b3(a) * b3(b);
+                const float wbar = h * (A * (cq[t] - cpr) - K2) + 2.0f * Bc * h * h * w * vq[t];
+                const float dc = cvp.x - cq[t];
+                const float ww = wbar * w;
+                cbar_c -= ww * sgn(dc) / E;
+                gbar = fmaf(ww * fabsf(dc), sl * iE2, gbar);
+                s_l = fmaf(ww * fabsf(dc), g * iE2, s_l);
+                const float S = fabsf((float)s * ((float)a * dzp.x + (float)b * dzp.y));
+                const float F = fmaf(sz, S, P.eps_z * n4.w);
+                s_z = fmaf(ww * fabsf(n4.w - zq[t]), S / (F * F), s_z);
+                if (w > 0.0f && xn[t] > 0.0f) s_n = fmaf(ww, logf(xn[t]), s_n);
+            }
+            const float Gb = g > 0.0f ? gbar / (2.0f * g) / sk : 0.0f;
+            D.coef[i] = make_float4(A, Bc, cpr, E);
+            D.aux[i] = make_float4(Gb, cbar_c, K2, 0.0f);
+        }
+    }
+    const double tz = block_sum((double)s_z, red);
+    const double tn = block_sum((double)s_n, red);
+    const double tl = block_sum((double)s_l, red);
+    if (threadIdx.x == 0) {
+        double* o = D.part + ((size_t)level * D.tiles + tile) * 3;
+        o[0] = tz;
+        o[1] = tn;
+        o[2] = tl;
+    }
+}
+
+__global__ __launch_bounds__(kSvgfBlock) void adjoint_b_kernel(const BwdBatch Bt, const SvgfK P, uint32_t level) {
+    const int j = find_job(Bt.tile0, (int)Bt.n, blockIdx.x);
+    const BwdDesc& D = Bt.d[j];
+    uint32_t x, y;
+    tile_xy(blockIdx.x - Bt.tile0[j], D.tiles_x, x, y);
+    if (x >= D.W || y >= D.H) return;
+    const uint32_t L = P.levels;
+    const int W = (int)D.W, H = (int)D.H, s = 1 << level;
+    const size_t i = (size_t)y * W + x;
+    float2* out = adj_out(D, level, L);
+    const float4 n4 = D.nz[i];
+    if (!(n4.w > 0.0f)) {
+        out[i] = make_float2(0.0f, 0.0f);
+        return;
+    }
+    const float2* cv = D.save + (size_t)level * W * H;
+    const float2 cvq = cv[i];
+    const float3 nq = f3(n4);
+    const float sz = P.sz[level], sn = P.sn[level];
+    float acc_c = D.aux[i].y, acc_v = 0.0f;
+#pragma unroll
+    for (int b = -2; b <= 2; ++b) {
+        const int py = (int)y - s * b;
+        if (py < 0 || py >= H) continue;
+#pragma unroll
+        for (int a = -2; a <= 2; ++a) {
+            const int px = (int)x - s * a;
+            if (px < 0 || px >= W) continue;
+            const size_t p = (size_t)py * W + px;
+            const float4 np4 = D.nz[p];
+            if (!(np4.w > 0.0f)) continue;
+            const float4 cf = D.coef[p];
+            const float h = b3(a) * b3(b);
+            const float Kp = D.aux[p].z;
+            if (a == 0 && b == 0) {
+                acc_c = fmaf(cf.x, h, acc_c);
+                acc_v = fmaf(cf.y, h * h, acc_v);
+                continue;
+            }
+            const float cp = cv[p].x;
+            const float w = w_depth(np4.w, n4.w, D.dz[p], a, b, s, sz, P.eps_z) * w_normal(f3(np4), nq, sn) *
+                            expf(-fabsf(cp - cvq.x) / cf.w);
+            const float wbar = h * (cf.x * (cvq.x - cf.z) - Kp) + 2.0f * cf.y * h * h * w * cvq.y;
+            acc_c += cf.x * h * w + wbar * w * sgn(cp - cvq.x) / cf.w;
+            acc_v = fmaf(cf.y * h * h, w * w, acc_v);
+        }
+    }
+    // adjoint of the 3x3 prefilter: v_q feeds g of every valid neighbour
+#pragma unroll
+    for (int b = -1; b <= 1; ++b)
+#pragma unroll
+        for (int a = -1; a <= 1; ++a) {
+            const int rx = (int)x + a, ry = (int)y + b;
+            if (rx < 0 || rx >= W || ry < 0 || ry >= H) continue;
+            const size_t r = (size_t)ry * W + rx;
+            if (!(D.nz[r].w > 0.0f)) continue;
+            acc_v = fmaf(D.aux[r].x, k3(a) * k3(b), acc_v);
+        }
+    out[i] = make_float2(acc_c, acc_v);
+}
+
+// grad_sigma[fam * L + l] = sum over frames and tiles, in a fixed order.
+__global__ __launch_bounds__(256) void sigma_reduce_kernel(const BwdBatch Bt, uint32_t L, float* grad_sigma,
+                                                           int accumulate) {
+    __shared__ double red[4];
+    const uint32_t o = blockIdx.x;  // fam * L + l
+    const uint32_t fam = o / L, l = o % L;
+    double acc = 0.0;
+    for (uint32_t f = 0; f < Bt.n; ++f) {
+        const BwdDesc& D = Bt.d[f];
+        const double* p = D.part + (size_t)l * D.tiles * 3 + fam;
+        for (uint32_t t = threadIdx.x; t < D.tiles; t += 256) acc += p[(size_t)t * 3];
+    }
+#pragma unroll
+    for (int k = 32; k > 0; k >>= 1) acc += __shfl_xor(acc, k, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double tot = red[0] + red[1] + red[2] + red[3];
+        grad_sigma[o] = accumulate ? (float)((double)grad_sigma[o] + tot) : (float)tot;
+    }
+}
+
+}  // namespace
+}  // namespace dhr
+
+extern "C" {
+
+dhr_status dhr_svgf_backward(dhr_ctx* ctx, const dhr_svgf_params* params, const dhr_svgf_bwd_frame* frames,
+                             uint32_t n_frames, float* grad_sigma, dhr_stream stream) {
+    using namespace dhr;
+    if (!ctx) return DHR_ERR_INVALID_ARG;
+    dhr_status st = svgf_check_params(ctx, params, "dhr_svgf_backward");
+    if (st != DHR_OK) return st;
+    if (!grad_sigma || (n_frames && !frames))
+        return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_backward: null pointer");
+    const uint32_t L = params->levels;
+    std::vector<BwdDesc> descs(n_frames);
+    for (uint32_t k = 0; k < n_frames; ++k) {
+        const dhr_svgf_bwd_frame& F = frames[k];
+        if (F.W < 1 || F.H < 1 || F.W > DHR_MAX_SIDE || F.H > DHR_MAX_SIDE)
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_backward: frame %u: bad size", k);
+        if (!F.save || !F.nz || !F.dz || !F.grad_out || !F.grad_cv || !F.work)
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_backward: frame %u: missing buffer", k);
+        if (!aligned8(F.save) || !aligned16(F.nz) || !aligned8(F.dz) || !aligned8(F.grad_cv) || !aligned16(F.work))
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_backward: frame %u: misaligned buffer", k);
+        const size_t HW = (size_t)F.W * F.H;
+        BwdDesc& d = descs[k];
+        std::memset(&d, 0, sizeof d);
+        d.W = F.W;
+        d.H = F.H;
+        d.tiles_x = (F.W + kSvgfTile - 1) / kSvgfTile;
+        d.tiles = d.tiles_x * ((F.H + kSvgfTile - 1) / kSvgfTile);
+        d.save = reinterpret_cast<const float2*>(F.save);
+        d.nz = reinterpret_cast<const float4*>(F.nz);
+        d.dz = reinterpret_cast<const float2*>(F.dz);
+        d.grad_out = F.grad_out;
+        d.grad_cv = reinterpret_cast<float2*>(F.grad_cv);
+        char* w = reinterpret_cast<char*>(F.work);
+        d.coef = reinterpret_cast<float4*>(w);
+        d.g0 = reinterpret_cast<float2*>(w + HW * 16);
+        d.g1 = reinterpret_cast<float2*>(w + HW * 24);
+        d.aux = reinterpret_cast<float4*>(w + HW * 32);
+        d.part = reinterpret_cast<double*>(w + HW * 48);
+    }
+    DeviceGuard g(ctx->device);
+    const SvgfK K = [&] {
+        SvgfK k;
+        std::memset(&k, 0, sizeof k);
+        k.levels = L;
+        for (int l = 0; l < DHR_MAX_LEVELS; ++l) {
+            k.sz[l] = params->sigma_z[l];
+            k.sn[l] = params->sigma_n[l];
+            k.sl[l] = params->sigma_l[l];
+        }
+        k.eps_z = params->eps_z_rel;
+        k.eps_l = params->eps_l;
+        return k;
+    }();
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (n_frames == 0) {
+        if (hipMemsetAsync(grad_sigma, 0, sizeof(float) * 3 * L, s) != hipSuccess)
+            return set_error(ctx, DHR_ERR_DEVICE, "dhr_svgf_backward: memset failed");
+        return DHR_OK;
+    }
+    for (size_t b0 = 0; b0 < descs.size(); b0 += kBwdMaxB) {
+        BwdBatch B;
+        std::memset(&B, 0, sizeof B);
+        const size_t n = std::min<size_t>(kBwdMaxB, descs.size() - b0);
+        B.n = (uint32_t)n;
+        uint64_t acc = 0;
+        for (size_t k = 0; k < n; ++k) {
+            B.tile0[k] = (uint32_t)acc;
+            B.d[k] = descs[b0 + k];
+            acc += descs[b0 + k].tiles;
+        }
+        B.tile0[n] = (uint32_t)acc;
+        for (int l = (int)L - 1; l >= 0; --l) {
+            hipLaunchKernelGGL(adjoint_a_kernel, dim3((uint32_t)acc), dim3(kSvgfBlock), 0, s, B, K, (uint32_t)l);
+            hipLaunchKernelGGL(adjoint_b_kernel, dim3((uint32_t)acc), dim3(kSvgfBlock), 0, s, B, K, (uint32_t)l);
+        }
+        hipLaunchKernelGGL(sigma_reduce_kernel, dim3(3 * L), dim3(256), 0, s, B, L, grad_sigma, b0 > 0 ? 1 : 0);
+        st = check_launch(ctx, "dhr_svgf_backward");
+        if (st != DHR_OK) return st;
+    }
+    return DHR_OK;
+}
+
+}  // extern "C"

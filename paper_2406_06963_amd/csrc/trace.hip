@@ -1,0 +1,481 @@
+// Ray kernels: the G-buffer of primary rays and the stochastic visibility
+// rays (ambient occlusion, Section 3.2; soft shadows, Section 3.1).
+//
+// Layout: one lane per pixel; a 128-lane workgroup covers a 16 x 8 tile and
+// each 64-lane wave an 8 x 8 square (coherent rays).  The traversal stack of
+// every lane lives in LDS (32 entries, interleaved by lane so consecutive
+// lanes hit consecutive banks).  Jobs of a ragged batch are passed by value
+// in the kernel arguments.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "device.h"
+#include "internal.h"
+
+namespace dhr {
+namespace {
+
+constexpr int kTileW = 16, kTileH = 8, kBlock = 128;
+
+struct CamD {
+    float eye[3], fwd[3], right[3], up[3];
+    float tx, ty;  // tan(fov/2) * aspect, tan(fov/2)
+};
+
+struct LightD {
+    uint32_t kind;
+    float v[3];
+    float k;
+    float radius;
+};
+
+struct TraceDesc {
+    const float4* nodes;
+    const float4* tris;
+    const float4* pos;
+    const float4* nz;
+    uint8_t* ao;
+    uint8_t* sh;
+    uint64_t* bits;
+    uint32_t W, H, tiles_x, frame, client, seed, n_ao, ao_off, n_shadow, n_lights;
+    float ao_r, eps_abs;
+    LightD lights[DHR_MAX_LIGHTS];
+};
+constexpr int kTraceMaxB = 12;
+using TraceBatch = Batch<TraceDesc, kTraceMaxB>;
+static_assert(sizeof(TraceBatch) <= 4000, "kernel arguments too large");
+
+struct GbufDesc {
+    const float4* nodes;
+    const float4* tris;
+    float4* pos;
+    float4* nz;
+    float2* dz;
+    float2* mv;
+    uint32_t W, H, tiles_x, has_prev;
+    CamD cur, prev;
+};
+constexpr int kGbufMaxB = 16;
+using GbufBatch = Batch<GbufDesc, kGbufMaxB>;
+static_assert(sizeof(GbufBatch) <= 4000, "kernel arguments too large");
+
+__device__ __forceinline__ void tile_pixel(uint32_t t, uint32_t tiles_x, uint32_t& x, uint32_t& y) {
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    x = (t % tiles_x) * kTileW + w * 8 + (lane & 7);
+    y = (t / tiles_x) * kTileH + (lane >> 3);
+}
+
+__device__ __forceinline__ float3 cam_dir(const CamD& c, float px, float py, uint32_t W, uint32_t H) {
+    const float sx = (2.0f * px / (float)W - 1.0f) * c.tx;
+    const float sy = (1.0f - 2.0f * py / (float)H) * c.ty;
+    const float3 d = f3(c.fwd[0] + c.right[0] * sx + c.up[0] * sy, c.fwd[1] + c.right[1] * sx + c.up[1] * sy,
+                        c.fwd[2] + c.right[2] * sx + c.up[2] * sy);
+    return normalize3(d);
+}
+
+// COUNT: the instrumented variant that also tallies rays, node visits, leaf
+// visits and triangle tests into `counters` (device uint64[4]).
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsigned long long* counters) {
+    __shared__ int stack[kStack * kBlock];
+    const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
+    const TraceDesc& D = B.d[j];
+    uint32_t x, y;
+    tile_pixel(blockIdx.x - B.tile0[j], D.tiles_x, x, y);
+    if (x >= D.W || y >= D.H) return;
+    const size_t HW = (size_t)D.W * D.H;
+    const size_t i = (size_t)y * D.W + x;
+    const float4 p4 = D.pos[i];
+    const float4 n4 = D.nz[i];
+    const bool valid = n4.w > 0.0f;
+    const float3 n = f3(n4);
+    const float3 p = f3(p4);
+    float eps = D.eps_abs;
+    if (!(eps > 0.0f)) eps = fmaxf(1e-3f * D.ao_r, fmaxf(fmaxf(fabsf(p.x), fabsf(p.y)), fabsf(p.z)) * 0x1p-17f);
+    const float3 o = p + n * eps;
+    int* stk = stack + threadIdx.x;
+    TravCount tc;
+    uint32_t n_rays = 0;
+
+    for (uint32_t st = 0; st <= D.n_lights; ++st) {
+        const uint32_t nr = st == 0 ? D.n_ao : D.n_shadow;
+        uint32_t cnt = 0;
+        uint64_t bits = 0;
+        if (!valid) {
+            cnt = nr;
+            bits = nr >= 64 ? ~0ull : ((1ull << nr) - 1ull);
+        } else {
+            for (uint32_t s = 0; s < nr; ++s) {
+                const float2 u = ray_uniforms(D.seed, D.client, x, y, D.frame, st, st == 0 ? D.ao_off + s : s);
+                Ray r;
+                r.o = o;
+                bool decided = false, occ = false;
+                if (st == 0) {
+                    r.d = sample_cosine(n, u.x, u.y);
+                    r.tmax = D.ao_r;
+                } else {
+                    const LightD& L = D.lights[st - 1];
+                    if (L.kind == 0) {
+                        r.d = sample_cone(f3(L.v[0], L.v[1], L.v[2]), L.k, u.x, u.y);
+                        r.tmax = __builtin_inff();
+                    } else {
+                        const float3 Dv = f3(L.v[0], L.v[1], L.v[2]) - o;
+                        const float dist = sqrtf(dot3(Dv, Dv));
+                        if (dist <= L.radius) {
+                            decided = true;
+                            occ = false;
+                        } else {
+                            const float3 axis = Dv * (1.0f / dist);
+                            const float rr = L.radius / dist;
+                            const float q = rr * rr;
+                            const float k = q / (1.0f + sqrtf(1.0f - q));
+                            r.d = sample_cone(axis, k, u.x, u.y);
+                            const float b = dot3(r.d, Dv);
+                            const float c = dist * dist - L.radius * L.radius;
+                            r.tmax = b - sqrtf(fmaxf(b * b - c, 0.0f));
+                        }
+                    }
+                    if (!decided && dot3(n, r.d) <= 0.0f) {
+                        decided = true;
+                        occ = true;
+                    }
+                }
+                if (!decided) {
+                    occ = any_hit<COUNT>(D.nodes, D.tris, r, stk, kBlock, &tc);
+                    if (COUNT) ++n_rays;
+                }
+                if (!occ) {
+                    ++cnt;
+                    if (s < 64) bits |= 1ull << s;
+                }
+            }
+        }
+        if (st == 0)
+            D.ao[i] = (uint8_t)cnt;
+        else
+            D.sh[(size_t)(st - 1) * HW + i] = (uint8_t)cnt;
+        if (D.bits) D.bits[(size_t)st * HW + i] = bits;
+    }
+    if (COUNT) {
+        // one vector atomic per lane (instrumented runs only)
+        atomicAdd(counters + 0, (unsigned long long)n_rays);
+        atomicAdd(counters + 1, (unsigned long long)tc.nodes);
+        atomicAdd(counters + 2, (unsigned long long)tc.leaves);
+        atomicAdd(counters + 3, (unsigned long long)tc.tris);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void gbuffer_kernel(const GbufBatch B) {
+    __shared__ int stack[kStack * kBlock];
+    const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
+    const GbufDesc& D = B.d[j];
+    uint32_t x, y;
+    tile_pixel(blockIdx.x - B.tile0[j], D.tiles_x, x, y);
+    if (x >= D.W || y >= D.H) return;
+    const size_t i = (size_t)y * D.W + x;
+    const CamD& C = D.cur;
+    const float3 eye = f3(C.eye[0], C.eye[1], C.eye[2]);
+    const float3 fwd = f3(C.fwd[0], C.fwd[1], C.fwd[2]);
+    const float3 d = cam_dir(C, x + 0.5f, y + 0.5f, D.W, D.H);
+    float t;
+    const int hit = closest_hit(D.nodes, D.tris, eye, d, t, stack + threadIdx.x, kBlock);
+    if (hit < 0) {
+        D.pos[i] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(DHR_MISS_ID));
+        D.nz[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        D.dz[i] = make_float2(0.0f, 0.0f);
+        D.mv[i] = make_float2(0.0f, 0.0f);
+        return;
+    }
+    const float4 v0 = D.tris[3 * hit + 0];
+    const float4 e1 = D.tris[3 * hit + 1];
+    const float4 e2 = D.tris[3 * hit + 2];
+    const float3 P = eye + d * t;
+    float3 nrm = normalize3(cross3(f3(e1), f3(e2)));
+    if (dot3(nrm, d) > 0.0f) nrm = nrm * -1.0f;
+    const float z = t * dot3(d, fwd);
+    D.pos[i] = make_float4(P.x, P.y, P.z, e1.w);
+    D.nz[i] = make_float4(nrm.x, nrm.y, nrm.z, z);
+    // depth of the hit plane through the pixel to the right and the one below
+    float dzv[2];
+    const float pd = dot3(f3(v0) - eye, nrm);
+    for (int k = 0; k < 2; ++k) {
+        const float3 d1 = cam_dir(C, x + 0.5f + (k == 0), y + 0.5f + (k == 1), D.W, D.H);
+        const float den = dot3(d1, nrm);
+        float out = 1e20f;
+        if (den != 0.0f) {
+            const float t1 = pd / den;
+            if (t1 > 0.0f) out = t1 * dot3(d1, fwd) - z;
+        }
+        dzv[k] = out;
+    }
+    D.dz[i] = make_float2(dzv[0], dzv[1]);
+    float2 mv = make_float2(__builtin_nanf(""), __builtin_nanf(""));
+    if (D.has_prev) {
+        const CamD& Q = D.prev;
+        const float3 v = P - f3(Q.eye[0], Q.eye[1], Q.eye[2]);
+        const float zc = dot3(v, f3(Q.fwd[0], Q.fwd[1], Q.fwd[2]));
+        if (zc > 0.0f) {
+            const float xc = dot3(v, f3(Q.right[0], Q.right[1], Q.right[2])) / zc;
+            const float yc = dot3(v, f3(Q.up[0], Q.up[1], Q.up[2])) / zc;
+            const float px = (xc / Q.tx + 1.0f) * 0.5f * (float)D.W;
+            const float py = (1.0f - yc / Q.ty) * 0.5f * (float)D.H;
+            mv = make_float2(px - (x + 0.5f), py - (y + 0.5f));
+        }
+    }
+    D.mv[i] = mv;
+}
+
+__global__ void philox_kernel(uint32_t k0, uint32_t k1, const uint4* __restrict__ ctr, uint4* __restrict__ out,
+                              uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = philox4x32_10(ctr[i], k0, k1);
+}
+
+// ------------------------------------------------------------------ host side
+
+bool make_cam(const dhr_camera& c, uint32_t W, uint32_t H, CamD* out) {
+    double e[3], f[3];
+    for (int k = 0; k < 3; ++k) {
+        e[k] = c.eye[k];
+        f[k] = (double)c.target[k] - (double)c.eye[k];
+    }
+    double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (!(fl > 0.0) || !std::isfinite(fl) || !(c.fov_y > 0.0f) || !(c.fov_y < 3.14f)) return false;
+    for (double& v : f) v /= fl;
+    double r[3] = {f[1] * 0.0 - f[2] * 1.0, f[2] * 0.0 - f[0] * 0.0, f[0] * 1.0 - f[1] * 0.0};  // fwd x (0,1,0)
+    double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(rl > 1e-9)) return false;
+    for (double& v : r) v /= rl;
+    double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
+    for (int k = 0; k < 3; ++k) {
+        out->eye[k] = (float)e[k];
+        out->fwd[k] = (float)f[k];
+        out->right[k] = (float)r[k];
+        out->up[k] = (float)u[k];
+    }
+    const double th = std::tan(0.5 * (double)c.fov_y);
+    out->tx = (float)(th * (double)W / (double)H);
+    out->ty = (float)th;
+    return true;
+}
+
+bool size_ok(uint32_t W, uint32_t H) { return W >= 1 && H >= 1 && W <= DHR_MAX_SIDE && H <= DHR_MAX_SIDE; }
+
+dhr_status check_trace_params(dhr_ctx* ctx, const dhr_trace_params& p) {
+    if (!size_ok(p.W, p.H)) return set_error(ctx, DHR_ERR_INVALID_ARG, "trace: image %ux%u outside 1..16384", p.W, p.H);
+    if (p.n_ao > 255) return set_error(ctx, DHR_ERR_INVALID_ARG, "trace: n_ao = %u > 255 (the count is one byte)", p.n_ao);
+    if (p.n_shadow > 255) return set_error(ctx, DHR_ERR_INVALID_ARG, "trace: n_shadow = %u > 255", p.n_shadow);
+    if (p.n_lights > DHR_MAX_LIGHTS) return set_error(ctx, DHR_ERR_INVALID_ARG, "trace: n_lights = %u > 8", p.n_lights);
+    if ((uint64_t)p.ao_sample_offset + p.n_ao > 65536)
+        return set_error(ctx, DHR_ERR_INVALID_ARG, "trace: AO sample index beyond 65535");
+    if (p.n_ao > 0 && !(p.ao_radius > 0.0f && std::isfinite(p.ao_radius)))
+        return set_error(ctx, DHR_ERR_INVALID_ARG, "trace: ao_radius must be positive");
+    if (!(p.eps_origin_abs >= 0.0f) || !std::isfinite(p.eps_origin_abs))
+        return set_error(ctx, DHR_ERR_INVALID_ARG, "trace: eps_origin_abs must be >= 0");
+    for (uint32_t l = 0; l < p.n_lights; ++l) {
+        const dhr_light& L = p.lights[l];
+        bool fin = std::isfinite(L.vec[0]) && std::isfinite(L.vec[1]) && std::isfinite(L.vec[2]);
+        if (L.kind == 0) {
+            double n2 = (double)L.vec[0] * L.vec[0] + (double)L.vec[1] * L.vec[1] + (double)L.vec[2] * L.vec[2];
+            if (!fin || !(n2 > 0.0) || !(L.one_minus_cos >= 0.0f && L.one_minus_cos <= 2.0f))
+                return set_error(ctx, DHR_ERR_INVALID_ARG, "trace: light %u: bad direction or cone", l);
+        } else if (L.kind == 1) {
+            if (!fin || !(L.radius > 0.0f) || !std::isfinite(L.radius))
+                return set_error(ctx, DHR_ERR_INVALID_ARG, "trace: light %u: bad sphere", l);
+        } else {
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "trace: light %u: unknown kind %u", l, L.kind);
+        }
+    }
+    return DHR_OK;
+}
+
+void fill_trace_desc(const dhr_bvh* bvh, const dhr_trace_params& p, const float* pos, const float* nz, uint8_t* ao,
+                     uint8_t* sh, uint64_t* bits, TraceDesc* d) {
+    std::memset(d, 0, sizeof *d);
+    d->nodes = bvh->nodes;
+    d->tris = bvh->tris;
+    d->pos = reinterpret_cast<const float4*>(pos);
+    d->nz = reinterpret_cast<const float4*>(nz);
+    d->ao = ao;
+    d->sh = sh;
+    d->bits = bits;
+    d->W = p.W;
+    d->H = p.H;
+    d->tiles_x = (p.W + kTileW - 1) / kTileW;
+    d->frame = p.frame;
+    d->client = p.client_id;
+    d->seed = p.seed;
+    d->n_ao = p.n_ao;
+    d->ao_off = p.ao_sample_offset;
+    d->n_shadow = p.n_shadow;
+    d->n_lights = p.n_lights;
+    d->ao_r = p.ao_radius;
+    d->eps_abs = p.eps_origin_abs;
+    for (uint32_t l = 0; l < p.n_lights; ++l) {
+        const dhr_light& L = p.lights[l];
+        d->lights[l].kind = L.kind;
+        d->lights[l].k = L.one_minus_cos;
+        d->lights[l].radius = L.radius;
+        if (L.kind == 0) {
+            double n = std::sqrt((double)L.vec[0] * L.vec[0] + (double)L.vec[1] * L.vec[1] + (double)L.vec[2] * L.vec[2]);
+            for (int k = 0; k < 3; ++k) d->lights[l].v[k] = (float)(L.vec[k] / n);
+        } else {
+            for (int k = 0; k < 3; ++k) d->lights[l].v[k] = L.vec[k];
+        }
+    }
+}
+
+uint32_t tiles_of(uint32_t W, uint32_t H) { return ((W + kTileW - 1) / kTileW) * ((H + kTileH - 1) / kTileH); }
+
+template <class D, int MAXB, class K, class... Extra>
+dhr_status launch_batches(dhr_ctx* ctx, const std::vector<D>& descs, const std::vector<uint32_t>& tiles, K kernel,
+                          int block, hipStream_t s, const char* what, Extra... extra) {
+    for (size_t b = 0; b < descs.size(); b += MAXB) {
+        Batch<D, MAXB> B;
+        std::memset(&B, 0, sizeof B);
+        const size_t n = std::min<size_t>(MAXB, descs.size() - b);
+        B.n = (uint32_t)n;
+        uint64_t acc = 0;
+        for (size_t k = 0; k < n; ++k) {
+            B.tile0[k] = (uint32_t)acc;
+            B.d[k] = descs[b + k];
+            acc += tiles[b + k];
+        }
+        B.tile0[n] = (uint32_t)acc;
+        if (acc == 0) continue;
+        if (acc > 0x7FFFFFFFull) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: batch too large", what);
+        hipLaunchKernelGGL(kernel, dim3((uint32_t)acc), dim3(block), 0, s, B, extra...);
+        dhr_status st = check_launch(ctx, what);
+        if (st != DHR_OK) return st;
+    }
+    return DHR_OK;
+}
+
+dhr_status trace_jobs(dhr_ctx* ctx, const dhr_trace_job* jobs, uint32_t n, const uint64_t* const* bits_per_job,
+                      dhr_stream stream, const char* what) {
+    std::vector<TraceDesc> descs(n);
+    std::vector<uint32_t> tiles(n);
+    for (uint32_t k = 0; k < n; ++k) {
+        const dhr_trace_job& J = jobs[k];
+        if (!J.bvh || J.bvh->ctx != ctx) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: bad bvh", what, k);
+        dhr_status st = check_trace_params(ctx, J.params);
+        if (st != DHR_OK) return st;
+        if (!J.pos || !J.nz || !J.ao_count || !aligned16(J.pos) || !aligned16(J.nz))
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: null or misaligned buffer", what, k);
+        if (J.params.n_lights > 0 && !J.shadow_count)
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: shadow_count is NULL", what, k);
+        uint64_t* bits = bits_per_job ? const_cast<uint64_t*>(bits_per_job[k]) : nullptr;
+        if (bits && (J.params.n_ao > 64 || J.params.n_shadow > 64 || !aligned8(bits)))
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: debug_ray_bits needs n <= 64 rays per stream", what);
+        fill_trace_desc(J.bvh, J.params, J.pos, J.nz, J.ao_count, J.shadow_count, bits, &descs[k]);
+        tiles[k] = tiles_of(J.params.W, J.params.H);
+    }
+    DeviceGuard g(ctx->device);
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(ctx->trace_counters);
+    if (cnt)
+        return launch_batches<TraceDesc, kTraceMaxB>(ctx, descs, tiles, trace_kernel<true>, kBlock,
+                                                     reinterpret_cast<hipStream_t>(stream), what, cnt);
+    return launch_batches<TraceDesc, kTraceMaxB>(ctx, descs, tiles, trace_kernel<false>, kBlock,
+                                                 reinterpret_cast<hipStream_t>(stream), what, cnt);
+}
+
+dhr_status gbuffer_jobs(dhr_ctx* ctx, const dhr_gbuffer_job* jobs, uint32_t n, dhr_stream stream, const char* what) {
+    std::vector<GbufDesc> descs(n);
+    std::vector<uint32_t> tiles(n);
+    for (uint32_t k = 0; k < n; ++k) {
+        const dhr_gbuffer_job& J = jobs[k];
+        if (!J.bvh || J.bvh->ctx != ctx) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: bad bvh", what, k);
+        if (!size_ok(J.W, J.H)) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: image %ux%u outside 1..16384", what, J.W, J.H);
+        if (!J.pos || !J.nz || !J.dz || !J.mv || !aligned16(J.pos) || !aligned16(J.nz) || !aligned8(J.dz) ||
+            !aligned8(J.mv))
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: null or misaligned buffer", what, k);
+        GbufDesc& d = descs[k];
+        std::memset(&d, 0, sizeof d);
+        if (!make_cam(J.cur, J.W, J.H, &d.cur) || (J.has_prev && !make_cam(J.prev, J.W, J.H, &d.prev)))
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: degenerate camera", what, k);
+        d.nodes = J.bvh->nodes;
+        d.tris = J.bvh->tris;
+        d.pos = reinterpret_cast<float4*>(J.pos);
+        d.nz = reinterpret_cast<float4*>(J.nz);
+        d.dz = reinterpret_cast<float2*>(J.dz);
+        d.mv = reinterpret_cast<float2*>(J.mv);
+        d.W = J.W;
+        d.H = J.H;
+        d.tiles_x = (J.W + kTileW - 1) / kTileW;
+        d.has_prev = J.has_prev ? 1u : 0u;
+        tiles[k] = tiles_of(J.W, J.H);
+    }
+    DeviceGuard g(ctx->device);
+    return launch_batches<GbufDesc, kGbufMaxB>(ctx, descs, tiles, gbuffer_kernel, kBlock,
+                                               reinterpret_cast<hipStream_t>(stream), what);
+}
+
+}  // namespace
+}  // namespace dhr
+
+extern "C" {
+
+dhr_status dhr_trace_visibility(dhr_ctx* ctx, const dhr_bvh* bvh, const dhr_trace_params* params, const float* pos,
+                                const float* nz, uint8_t* ao_count, uint8_t* shadow_count, uint64_t* debug_ray_bits,
+                                dhr_stream stream) {
+    if (!ctx) return DHR_ERR_INVALID_ARG;
+    if (!params) return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_trace_visibility: params is NULL");
+    dhr_trace_job job{bvh, *params, pos, nz, ao_count, shadow_count};
+    const uint64_t* bits[1] = {debug_ray_bits};
+    return dhr::trace_jobs(ctx, &job, 1, bits, stream, "dhr_trace_visibility");
+}
+
+dhr_status dhr_trace_visibility_batch(dhr_ctx* ctx, const dhr_trace_job* jobs, uint32_t n_jobs, dhr_stream stream) {
+    if (!ctx) return DHR_ERR_INVALID_ARG;
+    if (!jobs && n_jobs) return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_trace_visibility_batch: jobs is NULL");
+    return dhr::trace_jobs(ctx, jobs, n_jobs, nullptr, stream, "dhr_trace_visibility_batch");
+}
+
+dhr_status dhr_gbuffer(dhr_ctx* ctx, const dhr_bvh* bvh, const dhr_camera* cur, const dhr_camera* prev, uint32_t W,
+                       uint32_t H, float* pos, float* nz, float* dz, float* mv, dhr_stream stream) {
+    if (!ctx) return DHR_ERR_INVALID_ARG;
+    if (!cur) return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_gbuffer: camera is NULL");
+    dhr_gbuffer_job job;
+    std::memset(&job, 0, sizeof job);
+    job.bvh = bvh;
+    job.cur = *cur;
+    if (prev) job.prev = *prev;
+    job.has_prev = prev != nullptr;
+    job.W = W;
+    job.H = H;
+    job.pos = pos;
+    job.nz = nz;
+    job.dz = dz;
+    job.mv = mv;
+    return dhr::gbuffer_jobs(ctx, &job, 1, stream, "dhr_gbuffer");
+}
+
+dhr_status dhr_gbuffer_batch(dhr_ctx* ctx, const dhr_gbuffer_job* jobs, uint32_t n_jobs, dhr_stream stream) {
+    if (!ctx) return DHR_ERR_INVALID_ARG;
+    if (!jobs && n_jobs) return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_gbuffer_batch: jobs is NULL");
+    return dhr::gbuffer_jobs(ctx, jobs, n_jobs, stream, "dhr_gbuffer_batch");
+}
+
+dhr_status dhr_philox4x32_10(dhr_ctx* ctx, uint32_t k0, uint32_t k1, const uint32_t* ctr, uint32_t* out, uint64_t n,
+                             dhr_stream stream) {
+    if (!ctx) return DHR_ERR_INVALID_ARG;
+    if (n == 0) return DHR_OK;
+    if (!ctr || !out || !dhr::aligned16(ctr) || !dhr::aligned16(out) || n > (1ull << 36))
+        return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_philox4x32_10: bad buffers or size");
+    dhr::DeviceGuard g(ctx->device);
+    const uint32_t blocks = (uint32_t)((n + 255) / 256);
+    hipLaunchKernelGGL(dhr::philox_kernel, dim3(blocks), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), k0, k1,
+                       reinterpret_cast<const uint4*>(ctr), reinterpret_cast<uint4*>(out), n);
+    return dhr::check_launch(ctx, "dhr_philox4x32_10");
+}
+
+dhr_status dhr_set_trace_counters(dhr_ctx* ctx, uint64_t* counters) {
+    if (!ctx) return DHR_ERR_INVALID_ARG;
+    if (counters && !dhr::aligned8(counters))
+        return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_set_trace_counters: misaligned buffer");
+    ctx->trace_counters = counters;
+    return DHR_OK;
+}
+
+}  // extern "C"

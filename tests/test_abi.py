@@ -1,0 +1,51 @@
+"""The C-ABI library loads and exports every symbol include/dhr.h declares
+(no GPU needed; nothing is launched)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "dhr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dhr_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_method_calls():
+    names = declared()
+    for n in ("dhr_build_bvh", "dhr_trace_visibility", "dhr_svgf_filter", "dhr_svgf_backward"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2406_06963_amd import binding
+    L = binding.load()
+    missing = [n for n in declared() if not hasattr(L, n)]
+    assert not missing, missing
+    assert sorted(binding.EXPORTS) == declared()
+
+
+def test_struct_sizes_match_the_header():
+    # sizes of the by-value structs as the C compiler lays them out
+    from paper_2406_06963_amd import binding as B
+    assert ctypes.sizeof(B.dhr_light) == 24
+    assert ctypes.sizeof(B.dhr_trace_params) == 40 + 8 * 24 + 4
+    assert ctypes.sizeof(B.dhr_camera) == 28
+    assert ctypes.sizeof(B.dhr_svgf_params) == 4 * (3 + 24 + 4 + 4 + 1)
+
+
+def test_host_only_calls():
+    from paper_2406_06963_amd import binding as B
+    assert B.dhr_version().startswith("dhr")
+    p = B.svgf_params()
+    assert p.levels == 5 and abs(p.alpha - 0.2) < 1e-7 and p.sigma_n[0] == 128.0
+    assert B.dhr_svgf_workspace_bytes(1920, 1080, p, 0) == 2 * 1920 * 1080 * 8
+    # creating a context without a device fails cleanly with a status
+    import torch
+    if not torch.cuda.is_available():
+        try:
+            B.dhr_create(0)
+        except B.DhrError as e:
+            assert e.status in (3, 4)

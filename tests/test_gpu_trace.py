@@ -1,0 +1,257 @@
+"""GPU parity of the ray kernels against the oracle (needs an MI355X).
+
+* Philox: bit-identical streams.
+* G-buffer: object ids agree on all but <= 1e-4 of the pixels; positions,
+  normals and depths agree to fp32 intersection accuracy.
+* Visibility (per ray, through debug_ray_bits, on the oracle's G-buffer):
+  mismatch rate <= 1e-4 of the rays, on every workload at full size.
+* Closed forms on the GPU: lone plane fully visible, plane-beside-wall AO.
+* A ragged batch equals the per-job calls bitwise; runs are deterministic.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2406_06963_amd import workloads as wl
+from oracle_inputs import frames, popcount64, scene
+
+pytestmark = pytest.mark.gpu
+
+MISMATCH_RATE = 1e-4
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    from paper_2406_06963_amd import binding
+    binding.load()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    return B.dhr_create(0)
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+_bvh_cache = {}
+
+
+def gpu_bvh(B, ctx, name):
+    if name not in _bvh_cache:
+        sc, _ = scene(name)
+        _bvh_cache[name] = B.dhr_build_bvh(ctx, sc.tris, sc.obj_id)
+    return _bvh_cache[name]
+
+
+def test_philox_bit_identical(B, ctx):
+    import torch
+    rng = np.random.default_rng(7)
+    n = 1 << 20
+    ctr = rng.integers(0, 2 ** 32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:4096, :2] = np.stack(np.meshgrid(np.arange(64), np.arange(64)), -1).reshape(-1, 2)
+    out = torch.empty(n, 4, dtype=torch.int32, device="cuda")
+    B.dhr_philox4x32_10(ctx, (12345, 678), dev(ctr.view(np.int32)), out)
+    ref = orc.philox4x32_10((12345, 678), ctr)
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), ref)
+
+
+def test_bvh_info(B, ctx):
+    for name in ("spheres", "room", "terrain"):
+        info = gpu_bvh(B, ctx, name).info()
+        sc, _ = scene(name)
+        assert info["n_tris"] == sc.n_tris
+        assert info["depth"] <= 32 and info["max_leaf_size"] <= 4
+        print(name, info, flush=True)
+
+
+@pytest.mark.parametrize("preset", ["tiny", "room720", "terrain1080"])
+def test_gbuffer_parity(B, ctx, preset):
+    pr, fr = frames(preset, 2)
+    f = fr[1]
+    g = B.gbuffer_tensors(pr.W, pr.H)
+    B.dhr_gbuffer(ctx, gpu_bvh(B, ctx, pr.scene), fr[1]["cam"], fr[0]["cam"], pr.W, pr.H,
+                  g["pos"], g["nz"], g["dz"], g["mv"])
+    pos, nz, dz, mv = (g[k].cpu().numpy() for k in ("pos", "nz", "dz", "mv"))
+    ids, ids_o = pos[:, 3].view(np.uint32), orc.id_bits(f["pos"])
+    # a hit mismatch: another object, or another surface of the same object
+    # (fp32 and FP64 rays passing a silhouette on either side)
+    scale = np.abs(f["pos"][:, :3]).max(1) + 1.0
+    err = np.abs(pos[:, :3] - f["pos"][:, :3]).max(1) / scale
+    both = (ids != 0xFFFFFFFF) & (ids_o != 0xFFFFFFFF)
+    mism = (ids != ids_o) | (both & (err > 1e-3))
+    print(f"{preset}: {mism.sum()} of {mism.size} pixels hit another surface", flush=True)
+    assert mism.mean() <= 1e-4, mism.sum()
+    m = ~mism & (ids_o != 0xFFFFFFFF)
+    # elsewhere fp32 ray-plane intersection: relative error ~ eps / |cos| of the incidence angle
+    d = f["pos"][m, :3] - np.array(fr[1]["cam"].eye, np.float32)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    cosi = np.abs((d * f["nz"][m, :3]).sum(1))
+    err = err[m]
+    ok = cosi > 0.05
+    assert err[ok].max() <= 1e-5, err[ok].max()
+    assert err.max() <= 1e-3
+    assert np.abs(nz[m, :3] - f["nz"][m, :3]).max() <= 1e-5
+    assert (np.abs(nz[m, 3] - f["nz"][m, 3]) / f["nz"][m, 3])[ok].max() <= 1e-5
+    assert (nz[~m & ~mism, 3] == 0).all()
+    # dz: same sentinel decisions away from grazing pixels, else close
+    sent = f["dz"][m] >= 1e19
+    assert (sent[ok] == (dz[m][ok] >= 1e19)).all()
+    fin = ~sent & (dz[m] < 1e19)
+    rel = np.abs(dz[m][fin] - f["dz"][m][fin]) / (np.abs(f["dz"][m][fin]) + 1e-3 * f["nz"][m, 3:4].repeat(2, 1)[fin])
+    assert np.quantile(rel, 0.999) <= 1e-2
+    # motion: fp32 screen coordinates
+    assert np.nanmax(np.abs(mv[m] - f["mv"][m])) <= 5e-3
+
+
+def _trace_gpu(B, ctx, bvh, pr, f, n_ao, n_shadow, bits=True):
+    import torch
+    kw = dict(f["trace_kw"], n_ao=n_ao, n_shadow=n_shadow)
+    P = B.trace_params(pr.W, pr.H, **kw)
+    HW = pr.W * pr.H
+    L = len(kw["lights"])
+    ao = torch.empty(HW, dtype=torch.uint8, device="cuda")
+    sh = torch.empty(max(L, 1), HW, dtype=torch.uint8, device="cuda")
+    rb = torch.empty(1 + L, HW, dtype=torch.int64, device="cuda") if bits else None
+    B.dhr_trace_visibility(ctx, bvh, P, dev(f["pos"]), dev(f["nz"]), ao, sh, rb)
+    return ao.cpu().numpy(), sh.cpu().numpy()[:L], (rb.cpu().numpy().view(np.uint64) if bits else None)
+
+
+@pytest.mark.parametrize("preset,n_frames,n_ao,n_shadow", [
+    ("tiny", 8, 1, 1), ("tiny", 8, 32, 8), ("room720", 2, 1, 1), ("terrain1080", 2, 1, 2)])
+def test_visibility_parity(B, ctx, preset, n_frames, n_ao, n_shadow):
+    pr, fr = frames(preset, n_frames)
+    _, so = scene(pr.scene)
+    bvh = gpu_bvh(B, ctx, pr.scene)
+    rays = 0
+    bad = 0
+    for f in fr:
+        ao, sh, bits = _trace_gpu(B, ctx, bvh, pr, f, n_ao, n_shadow)
+        Po = orc.trace_params(pr.W, pr.H, **dict(f["trace_kw"], n_ao=n_ao, n_shadow=n_shadow))
+        ao_o, sh_o, bits_o = orc.trace(so, Po, f["pos"], f["nz"], ray_bits=True)
+        valid = f["nz"][:, 3] > 0
+        rays += valid.sum() * (n_ao + len(f["trace_kw"]["lights"]) * n_shadow)
+        bad += popcount64(bits ^ bits_o)
+        # counts are the popcounts of the bits
+        assert np.array_equal(ao, np.unpackbits(bits[0].view(np.uint8).reshape(-1, 8), axis=1).sum(1))
+    rate = bad / max(rays, 1)
+    print(f"{preset}: {bad} of {rays} rays differ (rate {rate:.2e})", flush=True)
+    assert rate <= MISMATCH_RATE
+
+
+def test_lone_plane_and_wall_closed_forms(B, ctx):
+    import math
+    # lone plane: every ray unoccluded
+    sc = wl.scene_plane()
+    so = orc.Scene(sc.tris, sc.obj_id)
+    bvh = B.dhr_build_bvh(ctx, sc.tris, sc.obj_id)
+    W, H = 96, 64
+    cam = wl.Camera((0.3, 2.0, 4.0), (0.0, 0.0, 0.0))
+    pos, nz, _, _ = orc.gbuffer(so, cam, None, W, H)
+    lights = [wl.directional_light((0.2, 1.0, 0.1), 1.0), wl.sphere_light((1.0, 3.0, -1.0), 0.5)]
+
+    class Pr:  # minimal preset-like record
+        pass
+    pr = Pr()
+    pr.W, pr.H = W, H
+    f = dict(pos=pos, nz=nz, trace_kw=dict(frame=0, seed=5, ao_radius=5.0, lights=lights))
+    ao, sh, _ = _trace_gpu(B, ctx, bvh, pr, f, 255, 16, bits=False)
+    assert (ao == 255).all() and (sh == 16).all()
+    # plane beside an infinite wall: V = 1 - (acos a - a sqrt(1-a^2)) / pi
+    sc = wl.scene_plane_wall(wall_x=0.0)
+    so = orc.Scene(sc.tris, sc.obj_id)
+    bvh = B.dhr_build_bvh(ctx, sc.tris, sc.obj_id)
+    W, H = 128, 128
+    cam = wl.Camera((-0.7, 2.5, 2.0), (-0.7, 0.0, -0.3))
+    pos, nz, _, _ = orc.gbuffer(so, cam, None, W, H)
+    counts = np.zeros(W * H)
+    frames_n = 4
+    for fr_i in range(frames_n):
+        f = dict(pos=pos, nz=nz, trace_kw=dict(frame=fr_i, seed=17, ao_radius=1.0, lights=[]))
+        pr.W, pr.H = W, H
+        ao, _, _ = _trace_gpu(B, ctx, bvh, pr, f, 255, 0, bits=False)
+        counts += ao
+    n = 255 * frames_n
+    d = -pos[:, 0].astype(np.float64)
+    a = np.clip(d, 0, 1)
+    V = 1 - (np.arccos(a) - a * np.sqrt(1 - a * a)) / math.pi
+    sel = (orc.id_bits(pos) == 0) & (nz[:, 3] > 0) & (d > 0)
+    bins = np.clip((d / 0.1).astype(int), 0, 12)
+    for b in range(13):
+        m = sel & (bins == b)
+        if m.sum() < 20:
+            continue
+        sigma = np.sqrt((V[m] * (1 - V[m])).sum() / n) / m.sum()
+        assert abs((counts[m] / n).mean() - V[m].mean()) <= 5 * sigma + 1e-12
+
+
+def test_batch_equals_single_and_deterministic(B, ctx):
+    import torch
+    jobs_in = [("tiny", 1), ("room720", 1), ("tiny", 0)]
+    singles = []
+    jobs = []
+    for name, fi in jobs_in:
+        pr, fr = frames(name, 2)
+        f = fr[fi]
+        bvh = gpu_bvh(B, ctx, pr.scene)
+        ao, sh, _ = _trace_gpu(B, ctx, bvh, pr, f, 4, 2, bits=False)
+        ao2, sh2, _ = _trace_gpu(B, ctx, bvh, pr, f, 4, 2, bits=False)
+        assert np.array_equal(ao, ao2) and np.array_equal(sh, sh2)
+        singles.append((ao, sh))
+        HW = pr.W * pr.H
+        L = len(f["trace_kw"]["lights"])
+        jobs.append(dict(bvh=bvh, params=B.trace_params(pr.W, pr.H, **dict(f["trace_kw"], n_ao=4, n_shadow=2)),
+                         pos=dev(f["pos"]), nz=dev(f["nz"]),
+                         ao_count=torch.empty(HW, dtype=torch.uint8, device="cuda"),
+                         shadow_count=torch.empty(L, HW, dtype=torch.uint8, device="cuda")))
+    B.dhr_trace_visibility_batch(ctx, jobs)
+    for j, (ao, sh) in zip(jobs, singles):
+        assert np.array_equal(j["ao_count"].cpu().numpy(), ao)
+        assert np.array_equal(j["shadow_count"].cpu().numpy(), sh)
+    # G-buffer batch vs single
+    gj = []
+    for name, fi in jobs_in:
+        pr, fr = frames(name, 2)
+        g = B.gbuffer_tensors(pr.W, pr.H)
+        gj.append(dict(bvh=gpu_bvh(B, ctx, pr.scene), cur=fr[fi]["cam"], prev=fr[0]["cam"], W=pr.W, H=pr.H, **g))
+    B.dhr_gbuffer_batch(ctx, gj)
+    for j in gj:
+        g = B.gbuffer_tensors(j["W"], j["H"])
+        B.dhr_gbuffer(ctx, j["bvh"], j["cur"], j["prev"], j["W"], j["H"], g["pos"], g["nz"], g["dz"], g["mv"])
+        for k in ("pos", "nz", "dz", "mv"):
+            assert torch.equal(torch.nan_to_num(g[k], 7.0), torch.nan_to_num(j[k], 7.0)), k
+
+
+def test_invalid_arguments_launch_nothing(B, ctx):
+    import torch
+    bvh = gpu_bvh(B, ctx, "spheres")
+    W, H = 8, 8
+    pos = torch.zeros(W * H, 4, device="cuda")
+    nz = torch.zeros(W * H, 4, device="cuda")
+    ao = torch.full((W * H,), 77, dtype=torch.uint8, device="cuda")
+    sh = torch.full((1, W * H), 77, dtype=torch.uint8, device="cuda")
+    bad = [B.trace_params(W, H, n_ao=256), B.trace_params(W, H, n_shadow=300),
+           B.trace_params(W, H, n_ao=1, ao_radius=0.0), B.trace_params(0, H),
+           B.trace_params(W, H, ao_sample_offset=65535, n_ao=2)]
+    for P in bad:
+        with pytest.raises(B.DhrError) as e:
+            B.dhr_trace_visibility(ctx, bvh, P, pos, nz, ao, sh)
+        assert e.value.status == 1
+    with pytest.raises(B.DhrError):
+        B.dhr_trace_visibility(ctx, bvh, B.trace_params(W, H), pos.view(-1)[1:], nz, ao, sh)
+    with pytest.raises(B.DhrError):
+        B.dhr_build_bvh(ctx, np.zeros((0, 3, 3), np.float32))
+    with pytest.raises(B.DhrError):
+        B.dhr_build_bvh(ctx, np.full((2, 3, 3), np.nan, np.float32))
+    torch.cuda.synchronize()
+    assert (ao == 77).all() and (sh == 77).all()
+    # invalid pixels count as fully visible
+    B.dhr_trace_visibility(ctx, bvh, B.trace_params(W, H, n_ao=7, n_shadow=3,
+                                                    lights=[wl.directional_light((0, 1, 0), 1.0)]), pos, nz, ao, sh)
+    torch.cuda.synchronize()
+    assert (ao == 7).all() and (sh == 3).all()

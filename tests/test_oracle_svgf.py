@@ -284,3 +284,21 @@ def test_adjoint_central_differences(orc):
             getattr(Pm, name)[l] = base - h
             fd = (loss(cv, Pp) - loss(cv, Pm)) / (2 * h)
             assert abs(fd - gs[fam, l]) <= 1e-6 * max(1.0, abs(gs[fam, l])), (name, l, fd, gs[fam, l])
+
+
+def test_tiny_negative_motion_uses_the_pixel_itself(orc):
+    # mv = -1e-10 px: the fraction 1 - 1e-10 rounds to 1 in fp32, so only tap
+    # 1 (at x - 1 + 1 = x) has a nonzero bilinear factor; the history must
+    # come from the pixel itself with weight one
+    W, H, n_ao = 6, 4, 4
+    pos, nz = _plane_frame(W, H)
+    rng = np.random.default_rng(12)
+    c = rng.random(W * H)
+    hist_in = np.column_stack([c, c, c * c, np.full(W * H, 3.0)]).astype(np.float32)
+    ao = np.full(W * H, 2, np.uint8)
+    P = orc.svgf_params()
+    mv = np.full((W * H, 2), -1e-10, np.float32)
+    out = orc.svgf_temporal(P, W, H, n_ao, ao, pos, nz, mv, pos, nz, hist_in, 0.001)
+    ref = orc.svgf_temporal(P, W, H, n_ao, ao, pos, nz, np.zeros_like(mv), pos, nz, hist_in, 0.001)
+    np.testing.assert_array_equal(out, ref)
+    assert (out[:, 3] == 4.0).all()
