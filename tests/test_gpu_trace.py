@@ -84,18 +84,17 @@ def test_gbuffer_parity(B, ctx, preset):
     scale = np.abs(f["pos"][:, :3]).max(1) + 1.0
     err = np.abs(pos[:, :3] - f["pos"][:, :3]).max(1) / scale
     both = (ids != 0xFFFFFFFF) & (ids_o != 0xFFFFFFFF)
-    mism = (ids != ids_o) | (both & (err > 1e-3))
+    mism = (ids != ids_o) | (both & (err > 1e-4))
     print(f"{preset}: {mism.sum()} of {mism.size} pixels hit another surface", flush=True)
     assert mism.mean() <= 1e-4, mism.sum()
     m = ~mism & (ids_o != 0xFFFFFFFF)
-    # elsewhere fp32 ray-plane intersection: relative error ~ eps / |cos| of the incidence angle
+    # elsewhere fp32 ray-plane intersection: relative error ~ 2^-23 x a few / |cos| of the incidence angle
     d = f["pos"][m, :3] - np.array(fr[1]["cam"].eye, np.float32)
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     cosi = np.abs((d * f["nz"][m, :3]).sum(1))
     err = err[m]
-    ok = cosi > 0.05
+    ok = cosi > 0.1
     assert err[ok].max() <= 1e-5, err[ok].max()
-    assert err.max() <= 1e-3
     assert np.abs(nz[m, :3] - f["nz"][m, :3]).max() <= 1e-5
     assert (np.abs(nz[m, 3] - f["nz"][m, 3]) / f["nz"][m, 3])[ok].max() <= 1e-5
     assert (nz[~m & ~mism, 3] == 0).all()
