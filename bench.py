@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--preset", default="terrain1080")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames of the oracle CPU baseline (0 = skip)")
     ap.add_argument("--no-counters", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=6.0, help="serving run per mode (0 = skip)")
+    ap.add_argument("--serve-clients", type=int, default=64)
+    ap.add_argument("--bwd-frames", type=int, default=16, help="frames of the differentiation run (0 = skip)")
     return ap.parse_args()
 
 
@@ -185,9 +188,129 @@ def main():
         "roofline_trace": roof_trace,
     }
 
+    if args.bwd_frames > 0:
+        line["differentiation"] = bench_backward(B, ctx, args.bwd_frames)
+    if args.serve_seconds > 0:
+        line["serving"] = bench_serving(B, ctx, args)
+        line["p99_ms"] = line["serving"]["batched"]["p99_ms"]
     if args.cpu_frames > 0:
         line["cpu_baseline"] = cpu_baseline(pr, scene, cams, lights, args)
     print(json.dumps(line), flush=True)
+
+
+def bench_backward(B, ctx, n_frames):
+    """Forward + backward of the 5-level stack over a batch of 720p frames of
+    the room workload (inputs from the path itself, MSE against 256-spp AO)."""
+    import torch
+
+    from paper_2406_06963_amd import workloads as wl
+    pr = wl.preset("room720")
+    W, H, HW = pr.W, pr.H, pr.W * pr.H
+    scene = wl.make_scene(pr.scene)
+    cams = wl.camera_path(pr.camera, n_frames, scene)
+    lights = wl.lights_for(pr.scene)
+    bvh = B.dhr_build_bvh(ctx, scene.tris, scene.obj_id)
+    P = B.svgf_params()
+    L = P.levels
+    gb = [B.gbuffer_tensors(W, H) for _ in range(n_frames)]
+    hist = [torch.empty(HW, 4, device="cuda") for _ in range(2)]
+    save = torch.empty(n_frames, L, HW, 2, device="cuda")
+    cv = torch.empty(n_frames, HW, 2, device="cuda")
+    target = torch.empty(n_frames, HW, device="cuda")
+    ao = torch.empty(HW, dtype=torch.uint8, device="cuda")
+    sh = torch.empty(1, HW, dtype=torch.uint8, device="cuda")
+    out = torch.empty(n_frames, HW, device="cuda")
+    for f in range(n_frames):
+        g = gb[f]
+        B.dhr_gbuffer(ctx, bvh, cams[f], cams[f - 1] if f else None, W, H, g["pos"], g["nz"], g["dz"], g["mv"])
+        B.dhr_trace_visibility(ctx, bvh, B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=1, ao_radius=pr.ao_radius,
+                                                        n_shadow=1, lights=lights), g["pos"], g["nz"], ao, sh)
+        fr = B.svgf_frame(W, H, 1, ao, g["pos"], g["nz"], g["dz"], g["mv"], gb[f - 1]["pos"] if f else None,
+                          gb[f - 1]["nz"] if f else None, hist[(f + 1) % 2] if f else None, hist[f % 2], out[f],
+                          B.pix_angle(cams[f], H), save=save[f])
+        B.dhr_svgf_filter(ctx, P, [fr])
+        cv[f] = save[f, 0]
+        # 256-spp reference: two 128-sample calls (sample offsets 0 and 128), another seed
+        acc = torch.zeros(HW, device="cuda")
+        for off in (0, 128):
+            B.dhr_trace_visibility(ctx, bvh, B.trace_params(W, H, frame=f, seed=9, n_ao=128, ao_sample_offset=off,
+                                                            ao_radius=pr.ao_radius, n_shadow=0),
+                                   g["pos"], g["nz"], ao, sh)
+            acc += ao.float()
+        target[f] = acc / 256.0
+    fwd = [B.spatial_frame(W, H, cv[f], gb[f]["nz"], gb[f]["dz"], out[f], save=save[f]) for f in range(n_frames)]
+    nb = B.dhr_svgf_workspace_bytes(W, H, P, 1)
+    work = torch.empty(n_frames, (nb + 15) // 16 * 4, device="cuda")
+    gcv = torch.empty(n_frames, HW, 2, device="cuda")
+    gs = torch.empty(3 * L, device="cuda")
+    valid = torch.stack([g["nz"][:, 3] > 0 for g in gb]).float()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    times = []
+    loss0 = None
+    for it in range(6):
+        e[0].record()
+        B.dhr_svgf_spatial_forward(ctx, P, fwd)
+        e[1].record()
+        go = (2.0 / valid.sum()) * (out - target) * valid
+        if it == 0:
+            loss0 = float(((out - target) ** 2 * valid).sum() / valid.sum())
+        bwd = [B.bwd_frame(W, H, save[f], gb[f]["nz"], gb[f]["dz"], go[f], gcv[f], work[f]) for f in range(n_frames)]
+        e[2].record()
+        B.dhr_svgf_backward(ctx, P, bwd, gs)
+        e[3].record()
+        torch.cuda.synchronize()
+        if it > 0:
+            times.append((e[0].elapsed_time(e[1]), e[2].elapsed_time(e[3])))
+    fw = sum(t[0] for t in times) / len(times)
+    bw = sum(t[1] for t in times) / len(times)
+    px = n_frames * HW
+    return {"workload": f"{n_frames} x {W}x{H} room frames, 5 levels, MSE vs 256-spp AO",
+            "forward_ms": fw, "backward_ms": bw, "fwd_bwd_ms": fw + bw,
+            "fwd_bwd_mpix_s": px / ((fw + bw) / 1e3) / 1e6, "mse": loss0,
+            "grad_sigma": gs.cpu().tolist()}
+
+
+def bench_serving(B, ctx, args):
+    """64 simulated clients (Poisson 30 Hz, delays U[0, 200] ms) served with
+    continuous batching, and the same trace served by per-client plain
+    launches (one request at a time, no fusion)."""
+    from paper_2406_06963_amd import serve as sv
+    from paper_2406_06963_amd import workloads as wl
+    scenes = {}
+    for name, r in (("spheres", 1.0), ("room", 0.5)):
+        sc = wl.make_scene(name)
+        scenes[name] = {"bvh": B.dhr_build_bvh(ctx, sc.tris, sc.obj_id), "lights": wl.lights_for(name),
+                        "ao_radius": r}
+    specs = sv.make_clients(args.serve_clients)
+    reqs = sv.request_trace(specs, args.serve_seconds)
+    res = {"clients": len(specs), "seconds": args.serve_seconds, "requests": len(reqs),
+           "offered_mpix_s": sum(s.W * s.H for s in specs) * 30.0 / 1e6}
+    for mode, kw in (("batched", dict(max_batch=16, max_inflight=3)), ("per_client", dict(max_batch=1, max_inflight=1))):
+        ex = sv.GpuExecutor(ctx, scenes, n_streams=kw["max_inflight"])
+        server = sv.Server(ex, budget_bytes=200e9, **kw)
+        for sp in specs:
+            server.connect(sp)
+        wall = sv.run_trace(server, reqs, args.serve_seconds)
+        res[mode] = server.stats.summary(wall)
+        res[mode]["resident_gb"] = server.used / 1e9
+        for sp in specs:
+            server.disconnect(sp.client_id)
+    res["speedup_frames_per_s"] = res["batched"]["frames_per_s"] / max(res["per_client"]["frames_per_s"], 1e-9)
+    # capacity: every client always has a fresh request (rate far above what
+    # the device can serve), batched vs per-client plain launches
+    sat = sv.request_trace(specs, min(args.serve_seconds, 3.0), rate_hz=400.0, max_delay_s=0.0)
+    for mode, kw in (("batched", dict(max_batch=16, max_inflight=3)), ("per_client", dict(max_batch=1, max_inflight=1))):
+        ex = sv.GpuExecutor(ctx, scenes, n_streams=kw["max_inflight"])
+        server = sv.Server(ex, budget_bytes=200e9, max_stale_s=10.0, **kw)
+        for sp in specs:
+            server.connect(sp)
+        wall = sv.run_trace(server, sat, min(args.serve_seconds, 3.0))
+        res["saturated_" + mode] = server.stats.summary(wall)
+        for sp in specs:
+            server.disconnect(sp.client_id)
+    res["saturated_speedup_frames_per_s"] = (res["saturated_batched"]["frames_per_s"]
+                                             / max(res["saturated_per_client"]["frames_per_s"], 1e-9))
+    return res
 
 
 def cpu_baseline(pr, scene, cams, lights, args):

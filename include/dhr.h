@@ -108,6 +108,8 @@ typedef struct {
 dhr_status dhr_build_bvh(dhr_ctx* ctx, const float* tris, const uint32_t* obj_id, uint32_t T,
                          const dhr_bvh_opts* opts, dhr_bvh** out);
 dhr_status dhr_bvh_get_info(const dhr_bvh* bvh, dhr_bvh_info* info);
+/* Frees the BVH's device memory (waits for work using it).  Valid before or
+ * after the context that built it has been destroyed. */
 void dhr_bvh_destroy(dhr_bvh* bvh);
 
 /* ------------------------------------------------------------------------

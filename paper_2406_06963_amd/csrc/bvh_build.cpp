@@ -320,6 +320,7 @@ dhr_status dhr_build_bvh(dhr_ctx* ctx, const float* tris, const uint32_t* obj_id
     dhr::DeviceGuard g(ctx->device);
     dhr_bvh* b = new dhr_bvh;
     b->ctx = ctx;
+    b->device = ctx->device;
     const size_t nb = hb.n_nodes * 4 * sizeof(float4), tb = 3ull * T * sizeof(float4);
     if (hipMalloc(&b->nodes, nb) != hipSuccess || hipMalloc(&b->tris, tb) != hipSuccess) {
         if (b->nodes) (void)hipFree(b->nodes);
@@ -359,7 +360,7 @@ dhr_status dhr_bvh_get_info(const dhr_bvh* bvh, dhr_bvh_info* info) {
 
 void dhr_bvh_destroy(dhr_bvh* bvh) {
     if (!bvh) return;
-    dhr::DeviceGuard g(bvh->ctx->device);
+    dhr::DeviceGuard g(bvh->device);
     (void)hipFree(bvh->nodes);
     (void)hipFree(bvh->tris);
     delete bvh;

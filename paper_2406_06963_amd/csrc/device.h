@@ -163,17 +163,25 @@ struct TravCount {
     uint32_t nodes = 0, leaves = 0, tris = 0;
 };
 
-// Any hit at 0 < t < tmax.  `stk` is this lane's column of an LDS stack with
-// row stride `stride`.  With COUNT the lane's work is tallied in `cnt`.
+// Traversal in the while-while form with leaf postponing: a lane that reaches
+// a leaf keeps it aside and goes on descending, and the wave only switches to
+// triangle tests once every lane holds a leaf (or has nothing left), so the
+// two kinds of work do not interleave within a wave.  The stack lives in LDS
+// (`stk`: this lane's column, row stride `stride`); the builder caps the depth
+// at kStack, and at most one entry is pushed per interior node on the path.
+constexpr int kDone = 0x7FFFFFFF;  // empty stack
+
+// Any hit at 0 < t < tmax.  With COUNT the lane's work is tallied in `cnt`.
 template <bool COUNT = false>
 __device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const float4* __restrict__ tris,
                                         const Ray& r, int* stk, int stride, TravCount* cnt = nullptr) {
     const float3 id = safe_inv(r.d);
     const float3 ood = f3(r.o.x * id.x, r.o.y * id.y, r.o.z * id.z);
     int sp = 0;
-    int node = 0;
-    while (true) {
-        if (node >= 0) {
+    int node = 0;   // interior index >= 0, leaf ref < 0, kDone
+    int leaf = 0;   // postponed leaf ref (< 0) or none (>= 0)
+    while (node != kDone || leaf < 0) {
+        while (node >= 0 && node != kDone) {
             bool h0, h1;
             float t0, t1;
             int c0, c1;
@@ -184,26 +192,31 @@ __device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const 
                 stk[sp * stride] = first0 ? c1 : c0;
                 ++sp;
                 node = first0 ? c0 : c1;
-                continue;
-            }
-            if (h0 || h1) {
+            } else if (h0 || h1) {
                 node = h0 ? c0 : c1;
-                continue;
+            } else {
+                node = sp ? stk[--sp * stride] : kDone;
             }
-        } else {
+            if (node < 0 && leaf >= 0) {
+                leaf = node;
+                node = sp ? stk[--sp * stride] : kDone;
+            }
+            if (!__any(leaf >= 0)) break;
+        }
+        while (leaf < 0) {
             int first, count;
-            leaf_range(node, first, count);
+            leaf_range(leaf, first, count);
             if (COUNT) ++cnt->leaves;
             for (int k = 0; k < count; ++k) {
                 if (COUNT) ++cnt->tris;
                 const float t = tri_t(tris, first + k, r.o, r.d);
                 if (t > 0.0f && t < r.tmax) return true;
             }
+            leaf = node;
+            if (node < 0) node = sp ? stk[--sp * stride] : kDone;
         }
-        if (sp == 0) return false;
-        --sp;
-        node = stk[sp * stride];
     }
+    return false;
 }
 
 // Closest hit at t > 0 (ties: lowest original triangle index).  Returns the
@@ -214,11 +227,12 @@ __device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, con
     const float3 ood = f3(o.x * id.x, o.y * id.y, o.z * id.z);
     int sp = 0;
     int node = 0;
+    int leaf = 0;
     int best = -1;
     uint32_t best_orig = 0xFFFFFFFFu;
     tbest = __builtin_inff();
-    while (true) {
-        if (node >= 0) {
+    while (node != kDone || leaf < 0) {
+        while (node >= 0 && node != kDone) {
             bool h0, h1;
             float t0, t1;
             int c0, c1;
@@ -228,15 +242,20 @@ __device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, con
                 stk[sp * stride] = first0 ? c1 : c0;
                 ++sp;
                 node = first0 ? c0 : c1;
-                continue;
-            }
-            if (h0 || h1) {
+            } else if (h0 || h1) {
                 node = h0 ? c0 : c1;
-                continue;
+            } else {
+                node = sp ? stk[--sp * stride] : kDone;
             }
-        } else {
+            if (node < 0 && leaf >= 0) {
+                leaf = node;
+                node = sp ? stk[--sp * stride] : kDone;
+            }
+            if (!__any(leaf >= 0)) break;
+        }
+        while (leaf < 0) {
             int first, count;
-            leaf_range(node, first, count);
+            leaf_range(leaf, first, count);
             for (int k = 0; k < count; ++k) {
                 const float t = tri_t(tris, first + k, o, d);
                 if (t > 0.0f && t <= tbest) {
@@ -248,11 +267,11 @@ __device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, con
                     }
                 }
             }
+            leaf = node;
+            if (node < 0) node = sp ? stk[--sp * stride] : kDone;
         }
-        if (sp == 0) return best;
-        --sp;
-        node = stk[sp * stride];
     }
+    return best;
 }
 
 }  // namespace dhr

@@ -20,7 +20,8 @@ struct dhr_ctx {
 // Device-resident BVH.  Node: 4 x 16 bytes (two child boxes + child refs);
 // triangle: 3 x 16 bytes (v0 + original index, e1 + object id, e2).
 struct dhr_bvh {
-    dhr_ctx* ctx = nullptr;
+    dhr_ctx* ctx = nullptr;  // identity only: never dereferenced after creation
+    int device = 0;
     float4* nodes = nullptr;
     float4* tris = nullptr;
     dhr_bvh_info info{};

@@ -112,10 +112,13 @@ __global__ __launch_bounds__(kSvgfBlock) void variance_kernel(const SvgfBatch B,
         // difference of the stored moments, exact in FP64, rounded once
         var = (float)fmax(0.0, (double)h.z - (double)h.y * (double)h.y);
     } else {
-        // pooled moments of the valid neighbours, depth/normal weights of level 0
+        // pooled moments of the valid neighbours, depth/normal weights of level 0;
+        // one pass with FP64 sums: var = sum w (mu2 - mu1^2) / sum w + (sum w mu1^2 / sum w - mbar^2)
         const int R = (int)P.R;
         const float2 dzp = D.dz[i];
-        double sw = 0.0, s1 = 0.0, s2 = 0.0;
+        const float3 np = f3(n4);
+        const float eps_zp = P.eps_z * n4.w;
+        double sw = 0.0, s1 = 0.0, s11 = 0.0, s2 = 0.0;
         for (int b = -R; b <= R; ++b) {
             const int qy = (int)y + b;
             if (qy < 0 || qy >= (int)D.H) continue;
@@ -127,92 +130,184 @@ __global__ __launch_bounds__(kSvgfBlock) void variance_kernel(const SvgfBatch B,
                 if (!(nq.w > 0.0f)) continue;
                 double w = 1.0;
                 if (a != 0 || b != 0)
-                    w = (double)(w_depth(n4.w, nq.w, dzp, a, b, 1, P.sz[0], P.eps_z) * w_normal(f3(n4), f3(nq), P.sn[0]));
+                    w = (double)fused_weight(depth_coef(dzp, a, b, 1, P.sz[0], eps_zp), 0.0f, n4.w, 0.0f, np, P.sn[0],
+                                             nq, 0.0f);
                 const float4 hq = D.hist_out[q];
+                const double m1 = (double)hq.y;
                 sw += w;
-                s1 = fma(w, (double)hq.y, s1);
-                s2 = fma(w, (double)hq.z - (double)hq.y * (double)hq.y, s2);
+                s1 = fma(w, m1, s1);
+                s11 = fma(w * m1, m1, s11);
+                s2 = fma(w, (double)hq.z - m1 * m1, s2);
             }
         }
         const double mbar = s1 / sw;
-        double s3 = 0.0;
-        for (int b = -R; b <= R; ++b) {
-            const int qy = (int)y + b;
-            if (qy < 0 || qy >= (int)D.H) continue;
-            for (int a = -R; a <= R; ++a) {
-                const int qx = (int)x + a;
-                if (qx < 0 || qx >= (int)D.W) continue;
-                const size_t q = (size_t)qy * D.W + qx;
-                const float4 nq = D.nz[q];
-                if (!(nq.w > 0.0f)) continue;
-                double w = 1.0;
-                if (a != 0 || b != 0)
-                    w = (double)(w_depth(n4.w, nq.w, dzp, a, b, 1, P.sz[0], P.eps_z) * w_normal(f3(n4), f3(nq), P.sn[0]));
-                const double d = (double)D.hist_out[q].y - mbar;
-                s3 = fma(w * d, d, s3);
-            }
-        }
-        var = (float)fmax(0.0, s2 / sw + s3 / sw);
+        var = (float)fmax(0.0, s2 / sw + fmax(0.0, s11 / sw - mbar * mbar));
     }
     dst[i] = make_float2(h.x, var);
 }
 
-__global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, const SvgfK P, uint32_t level) {
+// A-trous level at a large stride: every tap read from global memory (each
+// tap of a wave is a contiguous row segment, so loads stay coalesced; LDS
+// sub-image tiles would touch one cache line per pixel at these strides).
+template <int LEVEL>
+__global__ __launch_bounds__(kSvgfBlock) void atrous_direct_kernel(const SvgfBatch B, const SvgfK P) {
+    constexpr int s = 1 << LEVEL;
     const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
     const SvgfDesc& D = B.d[j];
-    uint32_t x, y;
-    tile_xy(blockIdx.x - B.tile0[j], D.tiles_x, x, y);
-    if (x >= D.W || y >= D.H) return;
-    const size_t i = (size_t)y * D.W + x;
-    const bool last = level + 1 == P.levels;
-    const float2* src = level_buf(D, level);
-    const float4 n4 = D.nz[i];
+    uint32_t ux, uy;
+    tile_xy(blockIdx.x - B.tile0[j], D.tiles_x, ux, uy);
+    if (ux >= D.W || uy >= D.H) return;
+    const int x = (int)ux, y = (int)uy, W = (int)D.W, H = (int)D.H;
+    const size_t i = (size_t)y * W + x;
+    const bool last = LEVEL + 1 == (int)P.levels;
+    const float2* __restrict__ src = level_buf(D, LEVEL);
+    const float4* __restrict__ nzb = D.nz;
+    const float4 n4 = nzb[i];
     if (!(n4.w > 0.0f)) {
         if (last)
             D.out[i] = 1.0f;
         else
-            level_buf(D, level + 1)[i] = make_float2(1.0f, 0.0f);
+            level_buf(D, LEVEL + 1)[i] = make_float2(1.0f, 0.0f);
         return;
     }
-    const int W = (int)D.W, H = (int)D.H, s = 1 << level;
-    // 3x3 prefilter of the variance
     float G = 0.0f, sk = 0.0f;
 #pragma unroll
     for (int b = -1; b <= 1; ++b)
 #pragma unroll
         for (int a = -1; a <= 1; ++a) {
-            const int qx = (int)x + a, qy = (int)y + b;
+            const int qx = x + a, qy = y + b;
             if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
             const size_t q = (size_t)qy * W + qx;
-            if (!(D.nz[q].w > 0.0f)) continue;
+            if (!(nzb[q].w > 0.0f)) continue;
             const float k = k3(a) * k3(b);
             G = fmaf(k, src[q].y, G);
             sk += k;
         }
     const float g = sqrtf(G / sk);
-    const float E = fmaf(P.sl[level], g, P.eps_l);
+    const float ke = kNegLog2e / fmaf(P.sl[LEVEL], g, P.eps_l);
     const float2 cvp = src[i];
     const float2 dzp = D.dz[i];
     const float3 np = f3(n4);
-    const float sz = P.sz[level], sn = P.sn[level];
-    float Dn = 0.0f, Sc = 0.0f, Sv = 0.0f;
+    const float sz = P.sz[LEVEL], sn = P.sn[LEVEL], eps_zp = P.eps_z * n4.w;
+    float Dn = 0.140625f, Sc = 0.0f, Sv = 0.140625f * 0.140625f * cvp.y;
 #pragma unroll
-    for (int b = -2; b <= 2; ++b) {
-        const int qy = (int)y + s * b;
-        if (qy < 0 || qy >= H) continue;
+    for (int tp = 0; tp < 12; ++tp) {
+        const int a = (tp + 13) % 5 - 2, b = (tp + 13) / 5 - 2;
+        const float kz = depth_coef(dzp, a, b, s, sz, eps_zp);
+        const float h = b3(a) * b3(b);
 #pragma unroll
-        for (int a = -2; a <= 2; ++a) {
-            const int qx = (int)x + s * a;
-            if (qx < 0 || qx >= W) continue;
+        for (int m = 0; m < 2; ++m) {
+            const int qx = x + (m ? -s * a : s * a), qy = y + (m ? -s * b : s * b);
+            if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
             const size_t q = (size_t)qy * W + qx;
-            const float4 nq = D.nz[q];
+            const float4 nq = nzb[q];
             if (!(nq.w > 0.0f)) continue;
             const float2 cvq = src[q];
-            float w = 1.0f;
-            if (a != 0 || b != 0)
-                w = w_depth(n4.w, nq.w, dzp, a, b, s, sz, P.eps_z) * w_normal(np, f3(nq), sn) *
-                    expf(-fabsf(cvp.x - cvq.x) / E);
-            const float hw = b3(a) * b3(b) * w;
+            const float hw = h * fused_weight(kz, ke, n4.w, cvp.x, np, sn, nq, cvq.x);
+            Dn += hw;
+            Sc = fmaf(hw, cvq.x - cvp.x, Sc);
+            Sv = fmaf(hw * hw, cvq.y, Sv);
+        }
+    }
+    const float inv = 1.0f / Dn;
+    const float cn = fmaf(Sc, inv, cvp.x);
+    const float vn = Sv * inv * inv;
+    if (last)
+        D.out[i] = cn;
+    else
+        level_buf(D, LEVEL + 1)[i] = make_float2(cn, vn);
+    if (LEVEL == (int)P.fb_level && D.hist_out) reinterpret_cast<float*>(D.hist_out)[4 * i] = cn;
+}
+
+// A-trous level LEVEL (stride s = 2^LEVEL).  The pixels congruent to
+// (ox, oy) mod s form a sub-image on which the dilated 5x5 stencil is dense:
+// a workgroup owns a 16 x 16 block of one sub-image and stages its 20 x 20
+// neighbourhood (geometry and (c, var)) in LDS once, so the 25 taps read LDS
+// instead of global memory.  Tile t of a frame: super-tile t / s^2 (16s x 16s
+// image pixels), sub-image t % s^2.
+template <int LEVEL>
+__global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, const SvgfK P) {
+    constexpr int s = 1 << LEVEL;
+    constexpr int T = kSvgfTile, TW = kSvgfTile + 4;
+    __shared__ float4 s_nz[TW * TW];
+    __shared__ float2 s_cv[TW * TW];
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int j = find_job(B.tile0, (int)B.n, lb);
+    const SvgfDesc& D = B.d[j];
+    const int t = (int)(lb - B.tile0[j]);
+    const int W = (int)D.W, H = (int)D.H;
+    const int nsx = (W + T * s - 1) / (T * s);
+    const int sub = t % (s * s), st = t / (s * s);
+    const int bx = (st % nsx) * T * s + sub % s, by = (st / nsx) * T * s + sub / s;
+    const float2* __restrict__ src = level_buf(D, LEVEL);
+    for (int e = threadIdx.x; e < TW * TW; e += kSvgfBlock) {
+        const int qx = bx + s * (e % TW - 2), qy = by + s * (e / TW - 2);
+        float4 nq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float2 cq = make_float2(0.0f, 0.0f);
+        if (qx >= 0 && qx < W && qy >= 0 && qy < H) {
+            const size_t q = (size_t)qy * W + qx;
+            nq = D.nz[q];
+            cq = src[q];
+        }
+        s_nz[e] = nq;
+        s_cv[e] = cq;
+    }
+    __syncthreads();
+    const int li = threadIdx.x % T, lj = threadIdx.x / T;
+    const int x = bx + s * li, y = by + s * lj;
+    if (x >= W || y >= H) return;
+    const size_t i = (size_t)y * W + x;
+    const int c = (lj + 2) * TW + (li + 2);
+    const bool last = LEVEL + 1 == (int)P.levels;
+    const float4 n4 = s_nz[c];
+    if (!(n4.w > 0.0f)) {
+        if (last)
+            D.out[i] = 1.0f;
+        else
+            level_buf(D, LEVEL + 1)[i] = make_float2(1.0f, 0.0f);
+        return;
+    }
+    // 3x3 prefilter of the variance (stride 1: in the tile only at level 0)
+    float G = 0.0f, sk = 0.0f;
+#pragma unroll
+    for (int b = -1; b <= 1; ++b)
+#pragma unroll
+        for (int a = -1; a <= 1; ++a) {
+            const float k = k3(a) * k3(b);
+            if (LEVEL == 0) {
+                const int e = c + b * TW + a;
+                if (!(s_nz[e].w > 0.0f)) continue;
+                G = fmaf(k, s_cv[e].y, G);
+            } else {
+                const int qx = x + a, qy = y + b;
+                if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
+                const size_t q = (size_t)qy * W + qx;
+                if (!(D.nz[q].w > 0.0f)) continue;
+                G = fmaf(k, src[q].y, G);
+            }
+            sk += k;
+        }
+    const float g = sqrtf(G / sk);
+    const float ke = kNegLog2e / fmaf(P.sl[LEVEL], g, P.eps_l);
+    const float2 cvp = s_cv[c];
+    const float2 dzp = D.dz[i];
+    const float3 np = f3(n4);
+    const float sz = P.sz[LEVEL], sn = P.sn[LEVEL], eps_zp = P.eps_z * n4.w;
+    // centre tap: w = 1
+    float Dn = 0.140625f, Sc = 0.0f, Sv = 0.140625f * 0.140625f * cvp.y;
+#pragma unroll
+    for (int tp = 0; tp < 12; ++tp) {
+        // the 12 taps after (0, 0) in raster order, and their mirrors
+        const int a = (tp + 13) % 5 - 2, b = (tp + 13) / 5 - 2;
+        const float kz = depth_coef(dzp, a, b, s, sz, eps_zp);
+        const float h = b3(a) * b3(b);
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const int e = m ? c - b * TW - a : c + b * TW + a;
+            const float4 nq = s_nz[e];
+            const float2 cvq = s_cv[e];
+            const float w = fused_weight(kz, ke, n4.w, cvp.x, np, sn, nq, cvq.x);
+            const float hw = nq.w > 0.0f ? h * w : 0.0f;
             Dn += hw;
             Sc = fmaf(hw, cvq.x - cvp.x, Sc);
             Sv = fmaf(hw * hw, cvq.y, Sv);
@@ -220,13 +315,30 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, c
     }
     // deviation form: exact where every tap equals the centre (a constant
     // region stays on the |c_p - c_q| kink instead of drifting by an ulp)
-    const float cn = cvp.x + Sc / Dn;
-    const float vn = Sv / (Dn * Dn);
+    const float inv = 1.0f / Dn;
+    const float cn = fmaf(Sc, inv, cvp.x);
+    const float vn = Sv * inv * inv;
     if (last)
         D.out[i] = cn;
     else
-        level_buf(D, level + 1)[i] = make_float2(cn, vn);
-    if (level == P.fb_level && D.hist_out) reinterpret_cast<float*>(D.hist_out)[4 * i] = cn;
+        level_buf(D, LEVEL + 1)[i] = make_float2(cn, vn);
+    if (LEVEL == (int)P.fb_level && D.hist_out) reinterpret_cast<float*>(D.hist_out)[4 * i] = cn;
+}
+
+// Levels 0-2 use LDS sub-image tiles, larger strides read taps directly.
+constexpr uint32_t kTiledLevels = 3;
+
+void launch_atrous(uint32_t level, dim3 grid, hipStream_t s, const SvgfBatch& B, const SvgfK& K) {
+    switch (level) {
+        case 0: hipLaunchKernelGGL(atrous_kernel<0>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 1: hipLaunchKernelGGL(atrous_kernel<1>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 2: hipLaunchKernelGGL(atrous_kernel<2>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 3: hipLaunchKernelGGL(atrous_direct_kernel<3>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 4: hipLaunchKernelGGL(atrous_direct_kernel<4>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 5: hipLaunchKernelGGL(atrous_direct_kernel<5>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 6: hipLaunchKernelGGL(atrous_direct_kernel<6>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        default: hipLaunchKernelGGL(atrous_direct_kernel<7>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+    }
 }
 
 // ------------------------------------------------------------------ host side
@@ -282,22 +394,42 @@ uint32_t svgf_tiles(uint32_t W, uint32_t H) { return svgf_tiles_x(W) * ((H + kSv
 
 bool sz_ok(uint32_t W, uint32_t H) { return W >= 1 && H >= 1 && W <= DHR_MAX_SIDE && H <= DHR_MAX_SIDE; }
 
-// Launches `pass` over all descriptors in chunks of kSvgfMaxB.
+// Tiles of an a-trous level: super-tiles of 16s x 16s pixels, s^2 sub-tiles each.
+uint32_t atrous_tiles(uint32_t W, uint32_t H, uint32_t level) {
+    if (level >= kTiledLevels) return svgf_tiles(W, H);
+    const uint32_t s = 1u << level, span = kSvgfTile * s;
+    return ((W + span - 1) / span) * ((H + span - 1) / span) * s * s;
+}
+
+// The batch of descriptors [b, b + n) with the tile prefix of `tiles(W, H)`.
+template <class TF>
+SvgfBatch make_batch(const std::vector<SvgfDesc>& descs, size_t b, size_t n, TF tiles) {
+    SvgfBatch B;
+    std::memset(&B, 0, sizeof B);
+    B.n = (uint32_t)n;
+    uint64_t acc = 0;
+    for (size_t k = 0; k < n; ++k) {
+        B.tile0[k] = (uint32_t)acc;
+        B.d[k] = descs[b + k];
+        acc += tiles(descs[b + k].W, descs[b + k].H);
+    }
+    B.tile0[n] = (uint32_t)acc;
+    return B;
+}
+
+// Launches the passes over all descriptors in chunks of kSvgfMaxB: `pixel`
+// passes on 16 x 16 tiles, then `levels` a-trous levels.
 template <class F>
-dhr_status for_chunks(dhr_ctx* ctx, const std::vector<SvgfDesc>& descs, const char* what, F launch) {
+dhr_status for_chunks(dhr_ctx* ctx, const std::vector<SvgfDesc>& descs, const char* what, uint32_t levels,
+                      hipStream_t s, const SvgfK& K, F pixel_passes) {
     for (size_t b = 0; b < descs.size(); b += kSvgfMaxB) {
-        SvgfBatch B;
-        std::memset(&B, 0, sizeof B);
         const size_t n = std::min<size_t>(kSvgfMaxB, descs.size() - b);
-        B.n = (uint32_t)n;
-        uint64_t acc = 0;
-        for (size_t k = 0; k < n; ++k) {
-            B.tile0[k] = (uint32_t)acc;
-            B.d[k] = descs[b + k];
-            acc += svgf_tiles(descs[b + k].W, descs[b + k].H);
+        const SvgfBatch B = make_batch(descs, b, n, svgf_tiles);
+        pixel_passes(B, dim3(B.tile0[n]));
+        for (uint32_t l = 0; l < levels; ++l) {
+            const SvgfBatch Bl = make_batch(descs, b, n, [l](uint32_t W, uint32_t H) { return atrous_tiles(W, H, l); });
+            launch_atrous(l, dim3(Bl.tile0[n]), s, Bl, K);
         }
-        B.tile0[n] = (uint32_t)acc;
-        launch(B, dim3((uint32_t)acc));
         dhr_status st = check_launch(ctx, what);
         if (st != DHR_OK) return st;
     }
@@ -373,10 +505,9 @@ dhr_status dhr_svgf_filter(dhr_ctx* ctx, const dhr_svgf_params* params, const dh
     DeviceGuard g(ctx->device);
     const SvgfK K = kparams(params);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    st = for_chunks(ctx, descs, "dhr_svgf_filter", [&](const SvgfBatch& B, dim3 grid) {
+    st = for_chunks(ctx, descs, "dhr_svgf_filter", K.levels, s, K, [&](const SvgfBatch& B, dim3 grid) {
         hipLaunchKernelGGL(temporal_kernel, grid, dim3(kSvgfBlock), 0, s, B, K);
         hipLaunchKernelGGL(variance_kernel, grid, dim3(kSvgfBlock), 0, s, B, K);
-        for (uint32_t l = 0; l < K.levels; ++l) hipLaunchKernelGGL(atrous_kernel, grid, dim3(kSvgfBlock), 0, s, B, K, l);
     });
     return st;
 }
@@ -418,9 +549,7 @@ dhr_status dhr_svgf_spatial_forward(dhr_ctx* ctx, const dhr_svgf_params* params,
         }
     }
     const SvgfK K = kparams(params);
-    return for_chunks(ctx, descs, "dhr_svgf_spatial_forward", [&](const SvgfBatch& B, dim3 grid) {
-        for (uint32_t l = 0; l < K.levels; ++l) hipLaunchKernelGGL(atrous_kernel, grid, dim3(kSvgfBlock), 0, s, B, K, l);
-    });
+    return for_chunks(ctx, descs, "dhr_svgf_spatial_forward", K.levels, s, K, [](const SvgfBatch&, dim3) {});
 }
 
 }  // extern "C"

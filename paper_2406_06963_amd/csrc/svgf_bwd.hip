@@ -102,57 +102,61 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_a_kernel(const BwdBatch Bt
             const float g = sqrtf(G / sk);
             const float sl = P.sl[level], sz = P.sz[level], sn = P.sn[level];
             const float E = fmaf(sl, g, P.eps_l);
+            const float iE = 1.0f / E;
+            const float ke = kNegLog2e * iE;
             const float2 cvp = cv[i];
             const float2 dzp = D.dz[i];
             const float3 np = f3(n4);
-            float wv[25], cq[25], vq[25], zq[25], xn[25];
+            const float eps_zp = P.eps_z * n4.w;
+            // sweep 1: tap weights (kept), normaliser and the level's outputs
+            float wv[25];
             float Dn = 0.0f, Sc = 0.0f, Sv = 0.0f;
 #pragma unroll
             for (int t = 0; t < 25; ++t) {
                 const int a = t % 5 - 2, b = t / 5 - 2;
                 wv[t] = -1.0f;
-                cq[t] = vq[t] = zq[t] = xn[t] = 0.0f;
                 const int qx = (int)x + s * a, qy = (int)y + s * b;
                 if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
                 const size_t q = (size_t)qy * W + qx;
                 const float4 nq = D.nz[q];
                 if (!(nq.w > 0.0f)) continue;
                 const float2 c2 = cv[q];
-                float w = 1.0f;
-                if (a != 0 || b != 0)
-                    w = w_depth(n4.w, nq.w, dzp, a, b, s, sz, P.eps_z) * w_normal(np, f3(nq), sn) *
-                        expf(-fabsf(cvp.x - c2.x) / E);
+                const float w = (a == 0 && b == 0)
+                                    ? 1.0f
+                                    : fused_weight(depth_coef(dzp, a, b, s, sz, eps_zp), ke, n4.w, cvp.x, np, sn, nq, c2.x);
                 wv[t] = w;
-                cq[t] = c2.x;
-                vq[t] = c2.y;
-                zq[t] = nq.w;
-                xn[t] = fminf(dot3(np, f3(nq)), 1.0f);
                 const float hw = b3(a) * b3(b) * w;
                 Dn += hw;
                 Sc = fmaf(hw, c2.x - cvp.x, Sc);
                 Sv = fmaf(hw * hw, c2.y, Sv);
             }
-            const float cpr = cvp.x + Sc / Dn, vpr = Sv / (Dn * Dn);
-            const float A = ab / Dn, Bc = bb / (Dn * Dn);
+            const float iD = 1.0f / Dn;
+            const float cpr = fmaf(Sc, iD, cvp.x), vpr = Sv * iD * iD;
+            const float A = ab * iD, Bc = bb * iD * iD;
             const float K2 = 2.0f * Bc * vpr * Dn;
             float cbar_c = 0.0f, gbar = 0.0f;
-            const float iE2 = 1.0f / (E * E);
+            const float iE2 = iE * iE;
+            // sweep 2: weight adjoints, the centre-role terms and the sigma partials
 #pragma unroll
             for (int t = 0; t < 25; ++t) {
                 const int a = t % 5 - 2, b = t / 5 - 2;
                 const float w = wv[t];
                 if (w < 0.0f || (a == 0 && b == 0)) continue;
+                const size_t q = (size_t)((int)y + s * b) * W + (size_t)((int)x + s * a);
+                const float4 nq = D.nz[q];
+                const float2 c2 = cv[q];
                 const float h = b3(a) * b3(b);
-                const float wbar = h * (A * (cq[t] - cpr) - K2) + 2.0f * Bc * h * h * w * vq[t];
-                const float dc = cvp.x - cq[t];
+                const float wbar = h * (A * (c2.x - cpr) - K2) + 2.0f * Bc * h * h * w * c2.y;
+                const float dc = cvp.x - c2.x;
                 const float ww = wbar * w;
-                cbar_c -= ww * sgn(dc) / E;
+                cbar_c -= ww * sgn(dc) * iE;
                 gbar = fmaf(ww * fabsf(dc), sl * iE2, gbar);
                 s_l = fmaf(ww * fabsf(dc), g * iE2, s_l);
                 const float S = fabsf((float)s * ((float)a * dzp.x + (float)b * dzp.y));
-                const float F = fmaf(sz, S, P.eps_z * n4.w);
-                s_z = fmaf(ww * fabsf(n4.w - zq[t]), S / (F * F), s_z);
-                if (w > 0.0f && xn[t] > 0.0f) s_n = fmaf(ww, logf(xn[t]), s_n);
+                const float iF = hw_rcp(fmaf(sz, S, eps_zp));
+                s_z = fmaf(ww * fabsf(n4.w - nq.w), S * iF * iF, s_z);
+                const float xn = fminf(dot3(np, f3(nq)), 1.0f);
+                if (w > 0.0f && xn > 0.0f) s_n = fmaf(ww, hw_log2(xn) * 0.6931471805599453f, s_n);
             }
             const float Gb = g > 0.0f ? gbar / (2.0f * g) / sk : 0.0f;
             D.coef[i] = make_float4(A, Bc, cpr, E);
@@ -210,10 +214,11 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_b_kernel(const BwdBatch Bt
                 continue;
             }
             const float cp = cv[p].x;
-            const float w = w_depth(np4.w, n4.w, D.dz[p], a, b, s, sz, P.eps_z) * w_normal(f3(np4), nq, sn) *
-                            expf(-fabsf(cp - cvq.x) / cf.w);
+            const float iE = 1.0f / cf.w;
+            const float w = fused_weight(depth_coef(D.dz[p], a, b, s, sz, P.eps_z * np4.w), kNegLog2e * iE, np4.w, cp,
+                                         f3(np4), sn, n4, cvq.x);
             const float wbar = h * (cf.x * (cvq.x - cf.z) - Kp) + 2.0f * cf.y * h * h * w * cvq.y;
-            acc_c += cf.x * h * w + wbar * w * sgn(cp - cvq.x) / cf.w;
+            acc_c += cf.x * h * w + wbar * w * sgn(cp - cvq.x) * iE;
             acc_v = fmaf(cf.y * h * h, w * w, acc_v);
         }
     }

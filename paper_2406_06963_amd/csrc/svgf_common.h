@@ -52,20 +52,41 @@ __device__ __forceinline__ void tile_xy(uint32_t t, uint32_t tiles_x, uint32_t& 
     y = (t / tiles_x) * kSvgfTile + (threadIdx.x / kSvgfTile);
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin by id.  This remap
+// (a bijection of [0, nb)) makes consecutive logical tiles share an XCD, so
+// tiles that read the same cache lines share its L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {
+    const uint32_t q = nb / 8, r = nb % 8, xcd = b % 8, k = b / 8;
+    return xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+}
+
 // 1-D taps: B3 spline (1,4,6,4,1)/16 and the (1,2,1)/4 variance prefilter
 __device__ __forceinline__ float b3(int a) { return a == 0 ? 0.375f : (a == 1 || a == -1 ? 0.25f : 0.0625f); }
 __device__ __forceinline__ float k3(int a) { return a == 0 ? 0.5f : 0.25f; }
 
-// depth term: exp(-|z_p - z_q| / (sigma_z |s (a dzx + b dzy)| + eps z_p))
-__device__ __forceinline__ float w_depth(float zp, float zq, float2 dzp, int a, int b, int s, float sz, float eps) {
+// All three edge-stopping terms as one power of two:
+//   w = exp2(kz |z_p - z_q| + ke |c_p - c_q| + sigma_n log2(n_p . n_q))
+// with kz = -log2(e) / (sigma_z S + eps_z z_p) (S shared by a tap and its
+// mirror) and ke = -log2(e) / (sigma_l g + eps_l); zero when n_p . n_q <= 0.
+// Hardware exp2 / log2 / rcp (about 1 ulp) replace the library calls and
+// divisions of the per-term form; the product is the same function.
+constexpr float kNegLog2e = -1.4426950408889634f;
+
+__device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// kz of the tap pair (a, b) / (-a, -b) at stride s
+__device__ __forceinline__ float depth_coef(float2 dzp, int a, int b, int s, float sz, float eps_zp) {
     const float S = fabsf((float)s * ((float)a * dzp.x + (float)b * dzp.y));
-    return expf(-fabsf(zp - zq) / fmaf(sz, S, eps * zp));
+    return kNegLog2e * hw_rcp(fmaf(sz, S, eps_zp));
 }
 
-// normal term: max(0, min(1, n_p . n_q))^sigma_n, 0 when the dot is <= 0
-__device__ __forceinline__ float w_normal(float3 np, float3 nq, float sn) {
-    const float x = fminf(dot3(np, nq), 1.0f);
-    return x > 0.0f ? exp2f(sn * log2f(x)) : 0.0f;
+__device__ __forceinline__ float fused_weight(float kz, float ke, float zp, float cp, float3 np, float sn, float4 nq,
+                                              float cq) {
+    const float x = fminf(dot3(np, f3(nq)), 1.0f);
+    const float e = fmaf(kz, fabsf(zp - nq.w), fmaf(ke, fabsf(cp - cq), sn * hw_log2(x)));
+    return x > 0.0f ? hw_exp2(e) : 0.0f;
 }
 
 }  // namespace dhr

@@ -31,11 +31,22 @@ __all__ = [
 ]
 
 
+def _f32(v) -> float:
+    return float(np.float32(v))
+
+
 @dataclass
 class Camera:
+    """Pinhole camera; every value is rounded to fp32 on construction (the
+    C interface carries fp32 cameras, so the oracle sees the same camera)."""
     eye: tuple
     target: tuple
     fov_y: float = math.radians(60.0)
+
+    def __post_init__(self):
+        self.eye = tuple(_f32(v) for v in self.eye)
+        self.target = tuple(_f32(v) for v in self.target)
+        self.fov_y = _f32(self.fov_y)
 
     def as_array(self) -> np.ndarray:
         return np.array([*self.eye, *self.target, self.fov_y], dtype=np.float64)

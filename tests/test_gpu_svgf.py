@@ -234,3 +234,48 @@ def test_svgf_invalid_arguments(B, ctx):
         B.dhr_svgf_filter(ctx, B.svgf_params(), [nao0])
     torch.cuda.synchronize()
     assert (out == 5.0).all()
+
+
+def test_autograd_stack_matches_oracle_and_fits(B, ctx):
+    import torch
+
+    from paper_2406_06963_amd.autograd import svgf_stack
+    pr, f, cv = _spatial_case("tiny", 3)
+    W, H = pr.W, pr.H
+    P = B.svgf_params()
+    nz = dev(f["nz"]).unsqueeze(0)
+    dz = dev(f["dz"]).unsqueeze(0)
+    c = dev(cv[:, 0]).unsqueeze(0).requires_grad_(True)
+    v = dev(cv[:, 1]).unsqueeze(0).requires_grad_(True)
+    sz = torch.full((5,), 1.0, device="cuda", requires_grad=True)
+    sn = torch.full((5,), 128.0, device="cuda", requires_grad=True)
+    sl = torch.full((5,), 4.0, device="cuda", requires_grad=True)
+    out = svgf_stack(c, v, nz, dz, sz, sn, sl, ctx, P, W, H)
+    go = np.random.default_rng(9).normal(size=W * H)
+    (out * dev(go.astype(np.float32)).unsqueeze(0)).sum().backward()
+    Po = orc.svgf_params()
+    gcv_o, gs_o = orc.svgf_spatial_vjp(Po, W, H, cv.astype(np.float64), f["nz"], f["dz"], go)
+    for t, ref in ((c.grad[0], gcv_o[:, 0]), (v.grad[0], gcv_o[:, 1])):
+        assert np.linalg.norm(t.cpu().numpy() - ref) <= 1e-3 * np.linalg.norm(ref)
+    for t, ref in ((sz.grad, gs_o[0]), (sn.grad, gs_o[1]), (sl.grad, gs_o[2])):
+        assert (np.abs(t.cpu().numpy() - ref) <= 1e-3 * np.abs(ref) + 1e-8).all()
+    # fitting the sigmas (in log space) against a 64-spp target lowers the loss
+    from oracle_inputs import scene
+    sc, so = scene(pr.scene)
+    Pt = orc.trace_params(W, H, **dict(f["trace_kw"], seed=77, n_ao=64))
+    ao_ref, _, _ = orc.trace(so, Pt, f["pos"], f["nz"])
+    target = dev((ao_ref / 64.0).astype(np.float32)).unsqueeze(0)
+    valid = dev((f["nz"][:, 3] > 0).astype(np.float32)).unsqueeze(0)
+    logs = torch.log(torch.tensor([[1.0] * 5, [128.0] * 5, [4.0] * 5], device="cuda")).requires_grad_(True)
+    opt = torch.optim.Adam([logs], lr=0.1)
+    losses = []
+    for _ in range(15):
+        opt.zero_grad()
+        s = logs.exp()
+        o = svgf_stack(c.detach(), v.detach(), nz, dz, s[0], s[1], s[2], ctx, P, W, H)
+        loss = (((o - target) ** 2) * valid).sum() / valid.sum()
+        loss.backward()
+        opt.step()
+        losses.append(float(loss))
+    print("sigma fit loss:", losses[0], "->", losses[-1], flush=True)
+    assert losses[-1] < losses[0]

@@ -79,30 +79,38 @@ def test_gbuffer_parity(B, ctx, preset):
                   g["pos"], g["nz"], g["dz"], g["mv"])
     pos, nz, dz, mv = (g[k].cpu().numpy() for k in ("pos", "nz", "dz", "mv"))
     ids, ids_o = pos[:, 3].view(np.uint32), orc.id_bits(f["pos"])
-    # a hit mismatch: another object, or another surface of the same object
-    # (fp32 and FP64 rays passing a silhouette on either side)
+    id_mism = ids != ids_o
+    print(f"{preset}: {id_mism.sum()} of {id_mism.size} pixels with another object id", flush=True)
+    assert id_mism.mean() <= 1e-4, id_mism.sum()
+    hit = ~id_mism & (ids_o != 0xFFFFFFFF)
+    assert (nz[~id_mism & (ids_o == 0xFFFFFFFF), 3] == 0).all()
+    # same object, but the fp32 and FP64 rays pass a silhouette of it on either
+    # side (another surface: a depth jump, or a position beyond the fp32 bound
+    # of the intersection) or land on either side of a shared edge (another
+    # facet of the same surface): discrete choices, bounded in number
     scale = np.abs(f["pos"][:, :3]).max(1) + 1.0
-    err = np.abs(pos[:, :3] - f["pos"][:, :3]).max(1) / scale
-    both = (ids != 0xFFFFFFFF) & (ids_o != 0xFFFFFFFF)
-    mism = (ids != ids_o) | (both & (err > 1e-4))
-    print(f"{preset}: {mism.sum()} of {mism.size} pixels hit another surface", flush=True)
-    assert mism.mean() <= 1e-4, mism.sum()
-    m = ~mism & (ids_o != 0xFFFFFFFF)
-    # elsewhere fp32 ray-plane intersection: relative error ~ 2^-23 x a few / |cos| of the incidence angle
-    d = f["pos"][m, :3] - np.array(fr[1]["cam"].eye, np.float32)
-    d /= np.linalg.norm(d, axis=1, keepdims=True)
-    cosi = np.abs((d * f["nz"][m, :3]).sum(1))
-    err = err[m]
-    ok = cosi > 0.1
-    assert err[ok].max() <= 1e-5, err[ok].max()
-    assert np.abs(nz[m, :3] - f["nz"][m, :3]).max() <= 1e-5
-    assert (np.abs(nz[m, 3] - f["nz"][m, 3]) / f["nz"][m, 3])[ok].max() <= 1e-5
-    assert (nz[~m & ~mism, 3] == 0).all()
+    perr = np.abs(pos[:, :3] - f["pos"][:, :3]).max(1) / scale
+    d = f["pos"][:, :3] - np.array(fr[1]["cam"].eye, np.float32)
+    d /= np.linalg.norm(d, axis=1, keepdims=True) + 1e-30
+    cosi = np.abs((d * f["nz"][:, :3]).sum(1))
+    # fp32 ray-plane intersection: relative error ~ 2^-23 x a few / |cos| of the incidence angle
+    bound = np.where(cosi > 0.1, 1e-5, 1e-3)
+    zrel = np.abs(nz[:, 3] - f["nz"][:, 3]) / np.maximum(f["nz"][:, 3], 1e-30)
+    other = hit & ((zrel > 1e-3) | (perr > bound))
+    facet = hit & ~other & (np.abs(nz[:, :3] - f["nz"][:, :3]).max(1) > 1e-4)
+    print(f"{preset}: other surface {other.sum()}, other facet {facet.sum()}", flush=True)
+    assert other.mean() <= 1e-4 and facet.mean() <= 1e-3
+    m = hit & ~other & ~facet
+    ok = m & (cosi > 0.1)
+    assert perr[m].max() <= 1e-3
+    assert np.abs(nz[m, :3] - f["nz"][m, :3]).max() <= 1e-4
+    assert zrel[ok].max() <= 1e-5
     # dz: same sentinel decisions away from grazing pixels, else close
-    sent = f["dz"][m] >= 1e19
-    assert (sent[ok] == (dz[m][ok] >= 1e19)).all()
-    fin = ~sent & (dz[m] < 1e19)
-    rel = np.abs(dz[m][fin] - f["dz"][m][fin]) / (np.abs(f["dz"][m][fin]) + 1e-3 * f["nz"][m, 3:4].repeat(2, 1)[fin])
+    sent_o = (f["dz"] >= 1e19)
+    sent_g = (dz >= 1e19)
+    assert (sent_o[ok] == sent_g[ok]).all()
+    fin = m[:, None] & ~sent_o & ~sent_g
+    rel = np.abs(dz - f["dz"])[fin] / (np.abs(f["dz"]) + 1e-3 * f["nz"][:, 3:4])[fin]
     assert np.quantile(rel, 0.999) <= 1e-2
     # motion: fp32 screen coordinates
     assert np.nanmax(np.abs(mv[m] - f["mv"][m])) <= 5e-3
