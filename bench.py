@@ -220,6 +220,7 @@ def bench_backward(B, ctx, n_frames):
     ao = torch.empty(HW, dtype=torch.uint8, device="cuda")
     sh = torch.empty(1, HW, dtype=torch.uint8, device="cuda")
     out = torch.empty(n_frames, HW, device="cuda")
+    fwork = torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device="cuda")
     for f in range(n_frames):
         g = gb[f]
         B.dhr_gbuffer(ctx, bvh, cams[f], cams[f - 1] if f else None, W, H, g["pos"], g["nz"], g["dz"], g["mv"])
@@ -227,7 +228,7 @@ def bench_backward(B, ctx, n_frames):
                                                         n_shadow=1, lights=lights), g["pos"], g["nz"], ao, sh)
         fr = B.svgf_frame(W, H, 1, ao, g["pos"], g["nz"], g["dz"], g["mv"], gb[f - 1]["pos"] if f else None,
                           gb[f - 1]["nz"] if f else None, hist[(f + 1) % 2] if f else None, hist[f % 2], out[f],
-                          B.pix_angle(cams[f], H), save=save[f])
+                          B.pix_angle(cams[f], H), save=save[f], work=fwork)
         B.dhr_svgf_filter(ctx, P, [fr])
         cv[f] = save[f, 0]
         # 256-spp reference: two 128-sample calls (sample offsets 0 and 128), another seed
@@ -238,7 +239,9 @@ def bench_backward(B, ctx, n_frames):
                                    g["pos"], g["nz"], ao, sh)
             acc += ao.float()
         target[f] = acc / 256.0
-    fwd = [B.spatial_frame(W, H, cv[f], gb[f]["nz"], gb[f]["dz"], out[f], save=save[f]) for f in range(n_frames)]
+    fwork_f = torch.empty(n_frames, (B.dhr_svgf_workspace_bytes(W, H, P, 0) + 15) // 16 * 4, device="cuda")
+    fwd = [B.spatial_frame(W, H, cv[f], gb[f]["nz"], gb[f]["dz"], out[f], save=save[f], work=fwork_f[f])
+           for f in range(n_frames)]
     nb = B.dhr_svgf_workspace_bytes(W, H, P, 1)
     work = torch.empty(n_frames, (nb + 15) // 16 * 4, device="cuda")
     gcv = torch.empty(n_frames, HW, 2, device="cuda")

@@ -272,7 +272,7 @@ typedef struct {
     float* save;                /* NULL or device float[levels][HW][2]: the input
                                    (c, var) of every level, for dhr_svgf_backward */
     float* work;                /* device scratch of dhr_svgf_workspace_bytes(W,H,p,0)
-                                   bytes; may be NULL when save is given */
+                                   bytes (16-byte aligned) */
     float pix;                  /* 2 tan(fov_y / 2) / H of the current camera */
 } dhr_svgf_frame;
 
@@ -289,7 +289,8 @@ typedef struct {
     const float *nz, *dz;
     float* out;                 /* device float[HW] */
     float* save;                /* NULL or device float[levels][HW][2] */
-    float* work;                /* dhr_svgf_workspace_bytes(W,H,p,0) bytes, or NULL with save */
+    float* work;                /* device scratch of dhr_svgf_workspace_bytes(W,H,p,0)
+                                   bytes (16-byte aligned) */
 } dhr_svgf_spatial_frame;
 dhr_status dhr_svgf_spatial_forward(dhr_ctx* ctx, const dhr_svgf_params* params,
                                     const dhr_svgf_spatial_frame* frames, uint32_t n_frames,
@@ -315,7 +316,8 @@ dhr_status dhr_svgf_backward(dhr_ctx* ctx, const dhr_svgf_params* params, const 
                              uint32_t n_frames, float* grad_sigma, dhr_stream stream);
 
 /* Scratch bytes one frame needs: which = 0 forward (filter / spatial), 1
- * backward. */
+ * backward.  Frames of one call need disjoint work buffers; a buffer may be
+ * reused by a later call on the same stream. */
 uint64_t dhr_svgf_workspace_bytes(uint32_t W, uint32_t H, const dhr_svgf_params* params, int which);
 
 /* Instrumentation for measurement: while `counters` (device uint64[4], or

@@ -34,7 +34,9 @@ class SVGFStack(torch.autograd.Function):
         save = torch.empty(F, L, W * H, 2, device=c.device, dtype=torch.float32)
         nz = nz.contiguous()
         dz = dz.contiguous()
-        frames = [B.spatial_frame(W, H, cv[f], nz[f], dz[f], out[f], save=save[f]) for f in range(F)]
+        nb = B.dhr_svgf_workspace_bytes(W, H, P, 0)
+        fwork = torch.empty(F, (nb + 15) // 16 * 4, device=c.device, dtype=torch.float32)
+        frames = [B.spatial_frame(W, H, cv[f], nz[f], dz[f], out[f], save=save[f], work=fwork[f]) for f in range(F)]
         B.dhr_svgf_spatial_forward(dctx, P, frames)
         fctx.save_for_backward(save, nz, dz)
         fctx.meta = (dctx, P, W, H, L, sigma_z.device)

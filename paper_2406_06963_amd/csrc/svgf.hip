@@ -51,30 +51,35 @@ __global__ __launch_bounds__(kSvgfBlock) void temporal_kernel(const SvgfBatch B,
         const float flx = floorf(mv.x), fly = floorf(mv.y);
         const float fx = mv.x - flx, fy = mv.y - fly;
         const float X0 = (float)x + flx, Y0 = (float)y + fly;
+        // the four bilinear taps' data are fetched up front (a tap that is
+        // inactive or outside the frame reads the pixel itself and is
+        // discarded), so the loads overlap instead of following the tests
+        float4 pn[4], hq[4], pp[4];
+        bool act[4];
 #pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
+        for (int t = 0; t < 4; ++t) {
+            const int k = t & 1, jj = t >> 1;
+            const float tx = X0 + (float)k, ty = Y0 + (float)jj;
+            act[t] = (k == 1 ? fx > 0.0f : fx < 1.0f) && (jj == 1 ? fy > 0.0f : fy < 1.0f) && tx >= 0.0f &&
+                     tx < (float)D.W && ty >= 0.0f && ty < (float)D.H;
+            const size_t q = act[t] ? (size_t)ty * D.W + (size_t)tx : i;
+            pn[t] = D.prev_nz[q];
+            hq[t] = D.hist_in[q];
+            pp[t] = D.prev_pos[q];
+        }
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                if (k == 1 ? !(fx > 0.0f) : !(fx < 1.0f)) continue;
-                if (jj == 1 ? !(fy > 0.0f) : !(fy < 1.0f)) continue;
-                const float tx = X0 + (float)k, ty = Y0 + (float)jj;
-                if (!(tx >= 0.0f && tx < (float)D.W && ty >= 0.0f && ty < (float)D.H)) continue;
-                const size_t q = (size_t)ty * D.W + (size_t)tx;
-                const float4 pn = D.prev_nz[q];
-                if (!(pn.w > 0.0f)) continue;
-                const float4 hq = D.hist_in[q];
-                if (!(hq.w > 0.0f)) continue;
-                const float4 pp = D.prev_pos[q];
-                if (P.use_obj && fbits(pp.w) != fbits(p4.w)) continue;
-                if (!tap_consistent(f3(n4), f3(p4), n4.w, pn, pp, P.cos_min, P.plane_px, D.pix)) continue;
-                const double b = (k ? (double)fx : 1.0 - (double)fx) * (jj ? (double)fy : 1.0 - (double)fy);
-                any = true;
-                wsum += b;
-                c = fma(b, (double)hq.x, c);
-                m1 = fma(b, (double)hq.y, m1);
-                m2 = fma(b, (double)hq.z, m2);
-                hmax = fmaxf(hmax, hq.w);
-            }
+        for (int t = 0; t < 4; ++t) {
+            const int k = t & 1, jj = t >> 1;
+            if (!act[t] || !(pn[t].w > 0.0f) || !(hq[t].w > 0.0f)) continue;
+            if (P.use_obj && fbits(pp[t].w) != fbits(p4.w)) continue;
+            if (!tap_consistent(f3(n4), f3(p4), n4.w, pn[t], pp[t], P.cos_min, P.plane_px, D.pix)) continue;
+            const double b = (k ? (double)fx : 1.0 - (double)fx) * (jj ? (double)fy : 1.0 - (double)fy);
+            any = true;
+            wsum += b;
+            c = fma(b, (double)hq[t].x, c);
+            m1 = fma(b, (double)hq[t].y, m1);
+            m2 = fma(b, (double)hq[t].z, m2);
+            hmax = fmaxf(hmax, hq[t].w);
         }
     }
     float4 h;
@@ -93,22 +98,56 @@ __global__ __launch_bounds__(kSvgfBlock) void temporal_kernel(const SvgfBatch B,
     D.hist_out[i] = h;
 }
 
+// Variance of level 0.  Workgroups with a pixel of short history stage the
+// moments and geometry of their 16 x 16 tile plus a 3-pixel rim in LDS for
+// the spatial fallback.
+constexpr int kVarRim = 3;
+
 __global__ __launch_bounds__(kSvgfBlock) void variance_kernel(const SvgfBatch B, const SvgfK P) {
+    constexpr int TW = kSvgfTile + 2 * kVarRim;
+    __shared__ float4 s_nz[TW * TW];  // zero for invalid or outside pixels
+    __shared__ float2 s_m[TW * TW];   // stored moments (m1, m2)
     const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
     const SvgfDesc& D = B.d[j];
     uint32_t x, y;
     tile_xy(blockIdx.x - B.tile0[j], D.tiles_x, x, y);
-    if (x >= D.W || y >= D.H) return;
-    const size_t i = (size_t)y * D.W + x;
-    float2* dst = level_buf(D, 0);
+    const int W = (int)D.W, H = (int)D.H;
+    const bool inside = x < D.W && y < D.H;
+    const size_t i = inside ? (size_t)y * D.W + x : 0;
     const float4 n4 = D.nz[i];
-    if (!(n4.w > 0.0f)) {
+    const float4 h = D.hist_out[i];
+    const bool valid = inside && n4.w > 0.0f;
+    const bool fallback = valid && !(h.w >= (float)P.var_min_h);
+    if (__syncthreads_or(fallback)) {
+        const int bx = (int)x - (int)(threadIdx.x % kSvgfTile) - kVarRim;
+        const int by = (int)y - (int)(threadIdx.x / kSvgfTile) - kVarRim;
+        stage_tile<TW * TW>(
+            [&](int e) {
+                const int qx = bx + e % TW, qy = by + e / TW;
+                Staged r{make_float4(0.0f, 0.0f, 0.0f, 0.0f), make_float2(0.0f, 0.0f)};
+                if (qx >= 0 && qx < W && qy >= 0 && qy < H) {
+                    const size_t q = (size_t)qy * W + qx;
+                    const float4 hq = D.hist_out[q];
+                    r.nz = D.nz[q];
+                    r.cv = make_float2(hq.y, hq.z);
+                }
+                return r;
+            },
+            [&](int e, const Staged& r) {
+                const bool ok = r.nz.w > 0.0f;
+                s_nz[e] = ok ? r.nz : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                s_m[e] = r.cv;
+            });
+        __syncthreads();
+    }
+    if (!inside) return;
+    float2* dst = level_buf(D, 0);
+    if (!valid) {
         dst[i] = make_float2(1.0f, 0.0f);
         return;
     }
-    const float4 h = D.hist_out[i];
     float var;
-    if (h.w >= (float)P.var_min_h) {
+    if (!fallback) {
         // difference of the stored moments, exact in FP64, rounded once
         var = (float)fmax(0.0, (double)h.z - (double)h.y * (double)h.y);
     } else {
@@ -118,32 +157,78 @@ __global__ __launch_bounds__(kSvgfBlock) void variance_kernel(const SvgfBatch B,
         const float2 dzp = D.dz[i];
         const float3 np = f3(n4);
         const float eps_zp = P.eps_z * n4.w;
+        const int c = (int)(threadIdx.x / kSvgfTile + kVarRim) * TW + (int)(threadIdx.x % kSvgfTile) + kVarRim;
         double sw = 0.0, s1 = 0.0, s11 = 0.0, s2 = 0.0;
         for (int b = -R; b <= R; ++b) {
-            const int qy = (int)y + b;
-            if (qy < 0 || qy >= (int)D.H) continue;
             for (int a = -R; a <= R; ++a) {
-                const int qx = (int)x + a;
-                if (qx < 0 || qx >= (int)D.W) continue;
-                const size_t q = (size_t)qy * D.W + qx;
-                const float4 nq = D.nz[q];
+                const int e = c + b * TW + a;
+                const float4 nq = s_nz[e];
                 if (!(nq.w > 0.0f)) continue;
                 double w = 1.0;
                 if (a != 0 || b != 0)
                     w = (double)fused_weight(depth_coef(dzp, a, b, 1, P.sz[0], eps_zp), 0.0f, n4.w, 0.0f, np, P.sn[0],
                                              nq, 0.0f);
-                const float4 hq = D.hist_out[q];
-                const double m1 = (double)hq.y;
+                const double m1 = (double)s_m[e].x;
                 sw += w;
                 s1 = fma(w, m1, s1);
                 s11 = fma(w * m1, m1, s11);
-                s2 = fma(w, (double)hq.z - m1 * m1, s2);
+                s2 = fma(w, (double)s_m[e].y - m1 * m1, s2);
             }
         }
         const double mbar = s1 / sw;
         var = (float)fmax(0.0, s2 / sw + fmax(0.0, s11 / sw - mbar * mbar));
     }
     dst[i] = make_float2(h.x, var);
+}
+
+// Prefilter of level `level` (used for levels read directly): for every pixel, ke from the 3x3 blur of
+// its input variance.  A workgroup covers 64 x 16 pixels (4 rows per lane)
+// and stages their 66 x 18 neighbourhood in LDS.  The previous level marked
+// invalid pixels with kNoVar.  Writes D.ke.
+constexpr int kPreTX = 64, kPreTY = 16;
+
+uint32_t prefilter_tiles(uint32_t W, uint32_t H) {
+    return ((W + kPreTX - 1) / kPreTX) * ((H + kPreTY - 1) / kPreTY);
+}
+
+__global__ __launch_bounds__(kSvgfBlock) void prefilter_kernel(const SvgfBatch B, const SvgfK P, uint32_t level) {
+    constexpr int CW = kPreTX + 2, CH = kPreTY + 2, RPL = kPreTY * kPreTX / kSvgfBlock;
+    __shared__ float s_v[CW * CH];
+    const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
+    const SvgfDesc& D = B.d[j];
+    const int t = (int)(blockIdx.x - B.tile0[j]);
+    const int W = (int)D.W, H = (int)D.H;
+    const int ntx = (W + kPreTX - 1) / kPreTX;
+    const int bx = (t % ntx) * kPreTX - 1, by = (t / ntx) * kPreTY - 1;
+    const float2* __restrict__ src = level_buf(D, level);
+    stage_tile<CW * CH>(
+        [&](int e) {
+            const int qx = bx + e % CW, qy = by + e / CW;
+            return (qx >= 0 && qx < W && qy >= 0 && qy < H) ? src[(size_t)qy * W + qx].y : kNoVar;
+        },
+        [&](int e, float v) { s_v[e] = v; });
+    __syncthreads();
+    const int li = threadIdx.x % kPreTX, lj = (threadIdx.x / kPreTX) * RPL;
+    const int x = bx + 1 + li;
+    if (x >= W) return;
+    const float sl = P.sl[level], eps_l = P.eps_l;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int y = by + 1 + lj + r;
+        if (y >= H) return;
+        float G = 0.0f, sk = 0.0f;
+#pragma unroll
+        for (int b = -1; b <= 1; ++b)
+#pragma unroll
+            for (int a = -1; a <= 1; ++a) {
+                const float v = s_v[(lj + r + 1 + b) * CW + li + 1 + a];
+                if (!has_var(v)) continue;
+                const float k = k3(a) * k3(b);
+                G = fmaf(k, v, G);
+                sk += k;
+            }
+        D.ke[(size_t)y * W + x] = sk > 0.0f ? ke_of(G, sk, sl, eps_l) : 0.0f;
+    }
 }
 
 // A-trous level at a large stride: every tap read from global memory (each
@@ -167,24 +252,10 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_direct_kernel(const SvgfBat
         if (last)
             D.out[i] = 1.0f;
         else
-            level_buf(D, LEVEL + 1)[i] = make_float2(1.0f, 0.0f);
+            level_buf(D, LEVEL + 1)[i] = make_float2(1.0f, kNoVar);
         return;
     }
-    float G = 0.0f, sk = 0.0f;
-#pragma unroll
-    for (int b = -1; b <= 1; ++b)
-#pragma unroll
-        for (int a = -1; a <= 1; ++a) {
-            const int qx = x + a, qy = y + b;
-            if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
-            const size_t q = (size_t)qy * W + qx;
-            if (!(nzb[q].w > 0.0f)) continue;
-            const float k = k3(a) * k3(b);
-            G = fmaf(k, src[q].y, G);
-            sk += k;
-        }
-    const float g = sqrtf(G / sk);
-    const float ke = kNegLog2e / fmaf(P.sl[LEVEL], g, P.eps_l);
+    const float ke = D.ke[i];
     const float2 cvp = src[i];
     const float2 dzp = D.dz[i];
     const float3 np = f3(n4);
@@ -219,8 +290,8 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_direct_kernel(const SvgfBat
     if (LEVEL == (int)P.fb_level && D.hist_out) reinterpret_cast<float*>(D.hist_out)[4 * i] = cn;
 }
 
-// A-trous level LEVEL (stride s = 2^LEVEL).  The pixels congruent to
-// (ox, oy) mod s form a sub-image on which the dilated 5x5 stencil is dense:
+// A-trous level LEVEL (stride s = 2^LEVEL; used for level 0).  The pixels
+// congruent to (ox, oy) mod s form a sub-image on which the dilated 5x5 stencil is dense:
 // a workgroup owns a 16 x 16 block of one sub-image and stages its 20 x 20
 // neighbourhood (geometry and (c, var)) in LDS once, so the 25 taps read LDS
 // instead of global memory.  Tile t of a frame: super-tile t / s^2 (16s x 16s
@@ -240,18 +311,22 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, c
     const int sub = t % (s * s), st = t / (s * s);
     const int bx = (st % nsx) * T * s + sub % s, by = (st / nsx) * T * s + sub / s;
     const float2* __restrict__ src = level_buf(D, LEVEL);
-    for (int e = threadIdx.x; e < TW * TW; e += kSvgfBlock) {
-        const int qx = bx + s * (e % TW - 2), qy = by + s * (e / TW - 2);
-        float4 nq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        float2 cq = make_float2(0.0f, 0.0f);
-        if (qx >= 0 && qx < W && qy >= 0 && qy < H) {
-            const size_t q = (size_t)qy * W + qx;
-            nq = D.nz[q];
-            cq = src[q];
-        }
-        s_nz[e] = nq;
-        s_cv[e] = cq;
-    }
+    stage_tile<TW * TW>(
+        [&](int e) {
+            const int qx = bx + s * (e % TW - 2), qy = by + s * (e / TW - 2);
+            Staged r{make_float4(0.0f, 0.0f, 0.0f, 0.0f), make_float2(0.0f, 0.0f)};
+            if (qx >= 0 && qx < W && qy >= 0 && qy < H) {
+                const size_t q = (size_t)qy * W + qx;
+                r.nz = D.nz[q];
+                r.cv = src[q];
+            }
+            return r;
+        },
+        [&](int e, const Staged& r) {
+            const bool ok = r.nz.w > 0.0f;
+            s_nz[e] = ok ? r.nz : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            s_cv[e] = ok ? r.cv : make_float2(0.0f, 0.0f);
+        });
     __syncthreads();
     const int li = threadIdx.x % T, lj = threadIdx.x / T;
     const int x = bx + s * li, y = by + s * lj;
@@ -264,31 +339,29 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, c
         if (last)
             D.out[i] = 1.0f;
         else
-            level_buf(D, LEVEL + 1)[i] = make_float2(1.0f, 0.0f);
+            level_buf(D, LEVEL + 1)[i] = make_float2(1.0f, kNoVar);
         return;
     }
-    // 3x3 prefilter of the variance (stride 1: in the tile only at level 0)
-    float G = 0.0f, sk = 0.0f;
+    // 3x3 prefilter of the variance: from the tile at level 0 (stride 1),
+    // from the prefilter pass at the other levels (invalid pixels were staged
+    // with z = 0)
+    float ke;
+    if (LEVEL == 0) {
+        float G = 0.0f, sk = 0.0f;
 #pragma unroll
-    for (int b = -1; b <= 1; ++b)
+        for (int b = -1; b <= 1; ++b)
 #pragma unroll
-        for (int a = -1; a <= 1; ++a) {
-            const float k = k3(a) * k3(b);
-            if (LEVEL == 0) {
+            for (int a = -1; a <= 1; ++a) {
                 const int e = c + b * TW + a;
                 if (!(s_nz[e].w > 0.0f)) continue;
+                const float k = k3(a) * k3(b);
                 G = fmaf(k, s_cv[e].y, G);
-            } else {
-                const int qx = x + a, qy = y + b;
-                if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
-                const size_t q = (size_t)qy * W + qx;
-                if (!(D.nz[q].w > 0.0f)) continue;
-                G = fmaf(k, src[q].y, G);
+                sk += k;
             }
-            sk += k;
-        }
-    const float g = sqrtf(G / sk);
-    const float ke = kNegLog2e / fmaf(P.sl[LEVEL], g, P.eps_l);
+        ke = ke_of(G, sk, P.sl[LEVEL], P.eps_l);
+    } else {
+        ke = D.ke[i];
+    }
     const float2 cvp = s_cv[c];
     const float2 dzp = D.dz[i];
     const float3 np = f3(n4);
@@ -304,13 +377,7 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, c
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
             const int e = m ? c - b * TW - a : c + b * TW + a;
-            const float4 nq = s_nz[e];
-            const float2 cvq = s_cv[e];
-            const float w = fused_weight(kz, ke, n4.w, cvp.x, np, sn, nq, cvq.x);
-            const float hw = nq.w > 0.0f ? h * w : 0.0f;
-            Dn += hw;
-            Sc = fmaf(hw, cvq.x - cvp.x, Sc);
-            Sv = fmaf(hw * hw, cvq.y, Sv);
+            accumulate_tap(h, kz, ke, n4.w, cvp.x, np, sn, s_nz[e], s_cv[e], Dn, Sc, Sv);
         }
     }
     // deviation form: exact where every tap equals the centre (a constant
@@ -325,17 +392,127 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, c
     if (LEVEL == (int)P.fb_level && D.hist_out) reinterpret_cast<float*>(D.hist_out)[4 * i] = cn;
 }
 
-// Levels 0-2 use LDS sub-image tiles, larger strides read taps directly.
-constexpr uint32_t kTiledLevels = 3;
+// A-trous level LEVEL >= 1 (stride s = 2^LEVEL) on row classes: a workgroup
+// owns 64 consecutive pixels of 4 rows that are s apart (rows congruent mod
+// s), so every tap of the dilated 5x5 stencil falls on 8 staged rows of
+// 64 + 4s consecutive pixels.  Staging reads whole row segments (coalesced at
+// any stride) and each staged pixel serves up to 20 taps from LDS.  Tile t of
+// a frame: column block t % tx, then row class, then block of 4s rows.
+constexpr int kRowsTX = 64, kRowsTY = kSvgfBlock / kRowsTX;
+
+__host__ __device__ constexpr uint32_t rows_tiles(uint32_t W, uint32_t H, int level) {
+    return ((W + kRowsTX - 1) / kRowsTX) * (1u << level) * ((H + (kRowsTY << level) - 1) / (kRowsTY << level));
+}
+
+template <int LEVEL>
+__global__ __launch_bounds__(kSvgfBlock) void atrous_rows_kernel(const SvgfBatch B, const SvgfK P) {
+    constexpr int s = 1 << LEVEL;
+    constexpr int CW = kRowsTX + 4 * s, CH = kRowsTY + 4, GW = kRowsTX + 2;
+    __shared__ float4 s_nz[CH * CW];
+    __shared__ float2 s_cv[CH * CW];
+    __shared__ float s_g[kRowsTY * 2 * GW];  // variance of the rows above and below each output row
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int j = find_job(B.tile0, (int)B.n, lb);
+    const SvgfDesc& D = B.d[j];
+    const int t = (int)(lb - B.tile0[j]);
+    const int W = (int)D.W, H = (int)D.H;
+    const int ntx = (W + kRowsTX - 1) / kRowsTX;
+    const int X = t % ntx, rest = t / ntx;
+    const int x0 = X * kRowsTX, y0 = (rest / s) * (kRowsTY * s) + rest % s;
+    const float2* __restrict__ src = level_buf(D, LEVEL);
+    stage_tile<CH * CW>(
+        [&](int e) {
+            const int qx = x0 - 2 * s + e % CW, qy = y0 + s * (e / CW - 2);
+            Staged r{make_float4(0.0f, 0.0f, 0.0f, 0.0f), make_float2(0.0f, 0.0f)};
+            if (qx >= 0 && qx < W && qy >= 0 && qy < H) {
+                const size_t q = (size_t)qy * W + qx;
+                r.nz = D.nz[q];
+                r.cv = src[q];
+            }
+            return r;
+        },
+        [&](int e, const Staged& r) {
+            const bool ok = r.nz.w > 0.0f;
+            s_nz[e] = ok ? r.nz : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            s_cv[e] = ok ? r.cv : make_float2(0.0f, 0.0f);
+        });
+    // the 3x3 variance prefilter needs the rows next to each output row (the
+    // previous level marked invalid pixels with kNoVar)
+    stage_tile<kRowsTY * 2 * GW>(
+        [&](int e) {
+            const int qx = x0 - 1 + e % GW, qy = y0 + s * (e / (2 * GW)) + ((e / GW) % 2 ? 1 : -1);
+            return (qx >= 0 && qx < W && qy >= 0 && qy < H) ? src[(size_t)qy * W + qx].y : kNoVar;
+        },
+        [&](int e, float v) { s_g[e] = v; });
+    __syncthreads();
+    const int li = threadIdx.x % kRowsTX, lj = threadIdx.x / kRowsTX;
+    const int x = x0 + li, y = y0 + s * lj;
+    if (x >= W || y >= H) return;
+    const size_t i = (size_t)y * W + x;
+    const int c = (lj + 2) * CW + 2 * s + li;
+    const bool last = LEVEL + 1 == (int)P.levels;
+    const float4 n4 = s_nz[c];
+    if (!(n4.w > 0.0f)) {
+        if (last)
+            D.out[i] = 1.0f;
+        else
+            level_buf(D, LEVEL + 1)[i] = make_float2(1.0f, kNoVar);
+        return;
+    }
+    float G = 0.0f, sk = 0.0f;
+#pragma unroll
+    for (int b = -1; b <= 1; ++b)
+#pragma unroll
+        for (int a = -1; a <= 1; ++a) {
+            float v;
+            if (b == 0)
+                v = s_nz[c + a].w > 0.0f ? s_cv[c + a].y : kNoVar;
+            else
+                v = s_g[(2 * lj + (b > 0)) * GW + li + 1 + a];
+            if (!has_var(v)) continue;
+            const float k = k3(a) * k3(b);
+            G = fmaf(k, v, G);
+            sk += k;
+        }
+    const float ke = ke_of(G, sk, P.sl[LEVEL], P.eps_l);
+    const float2 cvp = s_cv[c];
+    const float2 dzp = D.dz[i];
+    const float3 np = f3(n4);
+    const float sz = P.sz[LEVEL], sn = P.sn[LEVEL], eps_zp = P.eps_z * n4.w;
+    float Dn = 0.140625f, Sc = 0.0f, Sv = 0.140625f * 0.140625f * cvp.y;
+#pragma unroll
+    for (int tp = 0; tp < 12; ++tp) {
+        const int a = (tp + 13) % 5 - 2, b = (tp + 13) / 5 - 2;
+        const float kz = depth_coef(dzp, a, b, s, sz, eps_zp);
+        const float h = b3(a) * b3(b);
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const int e = m ? c - b * CW - s * a : c + b * CW + s * a;
+            accumulate_tap(h, kz, ke, n4.w, cvp.x, np, sn, s_nz[e], s_cv[e], Dn, Sc, Sv);
+        }
+    }
+    const float inv = 1.0f / Dn;
+    const float cn = fmaf(Sc, inv, cvp.x);
+    const float vn = Sv * inv * inv;
+    if (last)
+        D.out[i] = cn;
+    else
+        level_buf(D, LEVEL + 1)[i] = make_float2(cn, vn);
+    if (LEVEL == (int)P.fb_level && D.hist_out) reinterpret_cast<float*>(D.hist_out)[4 * i] = cn;
+}
+
+// Level 0 uses dense 16 x 16 tiles (its variance prefilter comes from the
+// same tile), levels 1-5 row classes, deeper levels read taps directly.
+constexpr uint32_t kRowsMaxLevel = 5;
 
 void launch_atrous(uint32_t level, dim3 grid, hipStream_t s, const SvgfBatch& B, const SvgfK& K) {
     switch (level) {
         case 0: hipLaunchKernelGGL(atrous_kernel<0>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
-        case 1: hipLaunchKernelGGL(atrous_kernel<1>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
-        case 2: hipLaunchKernelGGL(atrous_kernel<2>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
-        case 3: hipLaunchKernelGGL(atrous_direct_kernel<3>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
-        case 4: hipLaunchKernelGGL(atrous_direct_kernel<4>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
-        case 5: hipLaunchKernelGGL(atrous_direct_kernel<5>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 1: hipLaunchKernelGGL(atrous_rows_kernel<1>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 2: hipLaunchKernelGGL(atrous_rows_kernel<2>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 3: hipLaunchKernelGGL(atrous_rows_kernel<3>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 4: hipLaunchKernelGGL(atrous_rows_kernel<4>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 5: hipLaunchKernelGGL(atrous_rows_kernel<5>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
         case 6: hipLaunchKernelGGL(atrous_direct_kernel<6>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
         default: hipLaunchKernelGGL(atrous_direct_kernel<7>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
     }
@@ -396,9 +573,8 @@ bool sz_ok(uint32_t W, uint32_t H) { return W >= 1 && H >= 1 && W <= DHR_MAX_SID
 
 // Tiles of an a-trous level: super-tiles of 16s x 16s pixels, s^2 sub-tiles each.
 uint32_t atrous_tiles(uint32_t W, uint32_t H, uint32_t level) {
-    if (level >= kTiledLevels) return svgf_tiles(W, H);
-    const uint32_t s = 1u << level, span = kSvgfTile * s;
-    return ((W + span - 1) / span) * ((H + span - 1) / span) * s * s;
+    if (level >= 1 && level <= kRowsMaxLevel) return rows_tiles(W, H, (int)level);
+    return svgf_tiles(W, H);
 }
 
 // The batch of descriptors [b, b + n) with the tile prefix of `tiles(W, H)`.
@@ -425,8 +601,11 @@ dhr_status for_chunks(dhr_ctx* ctx, const std::vector<SvgfDesc>& descs, const ch
     for (size_t b = 0; b < descs.size(); b += kSvgfMaxB) {
         const size_t n = std::min<size_t>(kSvgfMaxB, descs.size() - b);
         const SvgfBatch B = make_batch(descs, b, n, svgf_tiles);
+        const SvgfBatch Bp = make_batch(descs, b, n, prefilter_tiles);
         pixel_passes(B, dim3(B.tile0[n]));
         for (uint32_t l = 0; l < levels; ++l) {
+            if (l > kRowsMaxLevel)
+                hipLaunchKernelGGL(prefilter_kernel, dim3(Bp.tile0[n]), dim3(kSvgfBlock), 0, s, Bp, K, l);
             const SvgfBatch Bl = make_batch(descs, b, n, [l](uint32_t W, uint32_t H) { return atrous_tiles(W, H, l); });
             launch_atrous(l, dim3(Bl.tile0[n]), s, Bl, K);
         }
@@ -450,7 +629,7 @@ extern "C" {
 uint64_t dhr_svgf_workspace_bytes(uint32_t W, uint32_t H, const dhr_svgf_params* params, int which) {
     const uint64_t HW = (uint64_t)W * H;
     const uint32_t L = params ? params->levels : 5;
-    if (which == 0) return 2 * HW * 8;
+    if (which == 0) return 2 * HW * 8 + HW * 4;   // (c, var) ping-pong + ke
     // adjoint: per-pixel coefficients (float4), two (c, v) adjoint buffers,
     // prefilter/centre terms (float4), and per-tile sigma partials (3 doubles
     // per level and tile)
@@ -470,7 +649,7 @@ dhr_status dhr_svgf_filter(dhr_ctx* ctx, const dhr_svgf_params* params, const dh
         const dhr_svgf_frame& F = frames[k];
         if (!sz_ok(F.W, F.H)) return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_filter: frame %u: bad size", k);
         if (F.n_ao == 0) return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_filter: frame %u: n_ao == 0", k);
-        if (!F.ao_count || !F.pos || !F.nz || !F.dz || !F.mv || !F.hist_out || !F.out || (!F.save && !F.work))
+        if (!F.ao_count || !F.pos || !F.nz || !F.dz || !F.mv || !F.hist_out || !F.out || !F.work)
             return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_filter: frame %u: missing buffer", k);
         if (F.hist_in && (!F.prev_pos || !F.prev_nz))
             return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_filter: frame %u: hist_in needs prev_pos/prev_nz", k);
@@ -500,6 +679,7 @@ dhr_status dhr_svgf_filter(dhr_ctx* ctx, const dhr_svgf_params* params, const dh
         d.out = F.out;
         d.save = reinterpret_cast<float2*>(F.save);
         d.work = reinterpret_cast<float2*>(F.work);
+        d.ke = reinterpret_cast<float*>(F.work) + (size_t)F.W * F.H * 4;
         d.pix = F.pix;
     }
     DeviceGuard g(ctx->device);
@@ -525,7 +705,7 @@ dhr_status dhr_svgf_spatial_forward(dhr_ctx* ctx, const dhr_svgf_params* params,
     for (uint32_t k = 0; k < n_frames; ++k) {
         const dhr_svgf_spatial_frame& F = frames[k];
         if (!sz_ok(F.W, F.H)) return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_spatial_forward: frame %u: bad size", k);
-        if (!F.cv_in || !F.nz || !F.dz || !F.out || (!F.save && !F.work))
+        if (!F.cv_in || !F.nz || !F.dz || !F.out || !F.work)
             return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_spatial_forward: frame %u: missing buffer", k);
         if (!aligned8(F.cv_in) || !aligned16(F.nz) || !aligned8(F.dz) || (F.save && !aligned8(F.save)) ||
             (F.work && !aligned8(F.work)))
@@ -540,6 +720,7 @@ dhr_status dhr_svgf_spatial_forward(dhr_ctx* ctx, const dhr_svgf_params* params,
         d.out = F.out;
         d.save = reinterpret_cast<float2*>(F.save);
         d.work = reinterpret_cast<float2*>(F.work);
+        d.ke = reinterpret_cast<float*>(F.work) + (size_t)F.W * F.H * 4;
         if (F.save) {
             if (F.save != F.cv_in &&
                 hipMemcpyAsync(F.save, F.cv_in, (size_t)F.W * F.H * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)

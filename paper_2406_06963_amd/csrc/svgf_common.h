@@ -35,6 +35,7 @@ struct SvgfDesc {
     float2* save;        // [levels][HW]
     float2* work;        // [2][HW]
     const float2* b0;    // level-0 input when it is not save[0]/work[0]
+    float* ke;           // [HW] prefiltered AO-value coefficient of the current level (in work)
     float pix;
 };
 constexpr int kSvgfMaxB = 24;
@@ -47,10 +48,47 @@ __device__ __forceinline__ float2* level_buf(const SvgfDesc& D, uint32_t l) {
     return D.save ? D.save + (size_t)l * HW : D.work + (size_t)(l & 1u) * HW;
 }
 
+// Variance written for invalid pixels by the a-trous levels, so the variance
+// prefilter of the next level finds valid neighbours from (c, var) alone.
+// Finite, so a zero tap weight times it stays zero.
+constexpr float kNoVar = -3.0e38f;
+__device__ __forceinline__ bool has_var(float v) { return v > -1.0e38f; }
+
+// ke = -log2(e) / (sigma_l g + eps_l) with g = sqrt of the 3x3 (1,2,1)/4 blur of
+// the variance over valid pixels (G and its weight sk accumulated by the caller)
+__device__ __forceinline__ float ke_of(float G, float sk, float sl, float eps_l) {
+    return -1.4426950408889634f / fmaf(sl, sqrtf(G / sk), eps_l);
+}
+
 __device__ __forceinline__ void tile_xy(uint32_t t, uint32_t tiles_x, uint32_t& x, uint32_t& y) {
     x = (t % tiles_x) * kSvgfTile + (threadIdx.x % kSvgfTile);
     y = (t / tiles_x) * kSvgfTile + (threadIdx.x / kSvgfTile);
 }
+
+// Fills an N-entry LDS tile: every lane first issues the loads of all its
+// entries (load(e) must be safe for every e < N), then stores them, so the
+// loads of one lane overlap instead of each waiting for the previous store.
+template <int N, class Load, class Store>
+__device__ __forceinline__ void stage_tile(Load load, Store store) {
+    constexpr int K = (N + kSvgfBlock - 1) / kSvgfBlock;
+    decltype(load(0)) v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = (int)threadIdx.x + k * kSvgfBlock;
+        if (N % kSvgfBlock == 0 || e < N) v[k] = load(e);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = (int)threadIdx.x + k * kSvgfBlock;
+        if (N % kSvgfBlock == 0 || e < N) store(e, v[k]);
+    }
+}
+
+// Geometry and (c, var) of one staged pixel
+struct Staged {
+    float4 nz;
+    float2 cv;
+};
 
 // Workgroups are dispatched to the 8 XCDs round-robin by id.  This remap
 // (a bijection of [0, nb)) makes consecutive logical tiles share an XCD, so
@@ -87,6 +125,20 @@ __device__ __forceinline__ float fused_weight(float kz, float ke, float zp, floa
     const float x = fminf(dot3(np, f3(nq)), 1.0f);
     const float e = fmaf(kz, fabsf(zp - nq.w), fmaf(ke, fabsf(cp - cq), sn * hw_log2(x)));
     return x > 0.0f ? hw_exp2(e) : 0.0f;
+}
+
+// One tap of a level whose staged neighbourhood holds a zero normal for
+// invalid pixels (so n_p . n_q = 0 and the weight vanishes): accumulates the
+// weight sum, the weighted deviation and the squared-weight variance.
+__device__ __forceinline__ void accumulate_tap(float h, float kz, float ke, float zp, float cp, float3 np, float sn,
+                                               float4 nq, float2 cvq, float& Dn, float& Sc, float& Sv) {
+    const float x = fminf(dot3(np, f3(nq)), 1.0f);
+    const float d = cvq.x - cp;
+    const float e = fmaf(kz, fabsf(zp - nq.w), fmaf(ke, fabsf(d), sn * hw_log2(x)));
+    const float hw = x > 0.0f ? h * hw_exp2(e) : 0.0f;
+    Dn += hw;
+    Sc = fmaf(hw, d, Sc);
+    Sv = fmaf(hw * hw, cvq.y, Sv);
 }
 
 }  // namespace dhr

@@ -41,7 +41,7 @@ def test_host_only_calls():
     assert B.dhr_version().startswith("dhr")
     p = B.svgf_params()
     assert p.levels == 5 and abs(p.alpha - 0.2) < 1e-7 and p.sigma_n[0] == 128.0
-    assert B.dhr_svgf_workspace_bytes(1920, 1080, p, 0) == 2 * 1920 * 1080 * 8
+    assert B.dhr_svgf_workspace_bytes(1920, 1080, p, 0) == 2 * 1920 * 1080 * 8 + 1920 * 1080 * 4
     # creating a context without a device fails cleanly with a status
     import torch
     if not torch.cuda.is_available():

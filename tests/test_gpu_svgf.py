@@ -45,7 +45,7 @@ def gpu_filter(B, ctx, P, pr, f, prev, hist_in, save=False):
     hist = torch.empty(W * H, 4, device="cuda")
     out = torch.empty(W * H, device="cuda")
     sv = torch.empty(P.levels, W * H, 2, device="cuda") if save else None
-    work = None if save else torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device="cuda")
+    work = torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device="cuda")
     fr = B.svgf_frame(W, H, pr.n_ao, dev(f["ao"]), dev(f["pos"]), dev(f["nz"]), dev(f["dz"]), dev(f["mv"]),
                       dev(prev["pos"]) if prev else None, dev(prev["nz"]) if prev else None, dev(hist_in),
                       hist, out, float(f["pix"]), save=sv, work=work)
@@ -124,7 +124,8 @@ def gpu_spatial_backward(B, ctx, P, W, H, cv, nz, dz, go, reps=1):
     HW = W * H
     out = torch.empty(HW, device="cuda")
     save = torch.empty(P.levels, HW, 2, device="cuda")
-    B.dhr_svgf_spatial_forward(ctx, P, [B.spatial_frame(W, H, dev(cv), dev(nz), dev(dz), out, save=save)])
+    fwork = torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device="cuda")
+    B.dhr_svgf_spatial_forward(ctx, P, [B.spatial_frame(W, H, dev(cv), dev(nz), dev(dz), out, save=save, work=fwork)])
     work = torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 1) // 4, device="cuda")
     res = []
     for _ in range(reps):
@@ -155,6 +156,31 @@ def test_backward_parity(B, ctx, preset, frame):
     err = np.abs(gs - gs_o)
     print(f"{preset}: sigma grads gpu {gs.ravel()} oracle {gs_o.ravel()}", flush=True)
     assert (err <= 1e-3 * np.abs(gs_o) + 1e-8).all(), err / (np.abs(gs_o) + 1e-8)
+
+
+@pytest.mark.parametrize("levels", [1, 3, 6, 8])
+def test_spatial_forward_every_level(B, ctx, levels):
+    """Level counts 1..8 reach every kernel form (dense tile at level 0, row
+    classes at strides 2..32, direct taps and the separate prefilter at 64 and
+    128): the output and every saved level's (c, var) on valid pixels match
+    the oracle."""
+    import torch
+    pr, f, cv = _spatial_case("room720", 1, jitter=False)
+    W, H = pr.W, pr.H
+    sz, sn, sl = _sigmas(levels, 11)
+    P = B.svgf_params(levels=levels, sigma_z=sz, sigma_n=sn, sigma_l=sl)
+    Po = orc.svgf_params(levels=levels, sigma_z=sz, sigma_n=sn, sigma_l=sl)
+    out = torch.empty(W * H, device="cuda")
+    save = torch.empty(levels, W * H, 2, device="cuda")
+    work = torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device="cuda")
+    B.dhr_svgf_spatial_forward(ctx, P, [B.spatial_frame(W, H, dev(cv), dev(f["nz"]), dev(f["dz"]), out, save=save,
+                                                        work=work)])
+    ref, ref_save = orc.svgf_spatial(Po, W, H, cv.astype(np.float64), f["nz"], f["dz"], save=True)
+    err = np.abs(out.cpu().numpy() - ref).max()
+    valid = f["nz"].reshape(-1, 4)[:, 3] > 0
+    lv = np.abs(save.cpu().numpy()[:, valid] - ref_save[:, valid]).max(axis=(1, 2))
+    print(f"levels {levels}: max |out - oracle| {err:.2e}; per saved level {lv}", flush=True)
+    assert err <= ATOL and (lv <= ATOL).all()
 
 
 def test_backward_vs_central_differences(B, ctx):
