@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="serving run per mode (0 = skip)")
     ap.add_argument("--serve-clients", type=int, default=64)
     ap.add_argument("--bwd-frames", type=int, default=16, help="frames of the differentiation run (0 = skip)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="before the steps, copy a buffer of this many MiB three times (a plain copy kernel of "
+                         "known size, to calibrate hardware byte counters; 0 = skip)")
     return ap.parse_args()
 
 
@@ -58,8 +61,8 @@ def svgf_bytes_per_px(levels: int) -> int:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
-              "(serving shards by client, one GPU each)", file=sys.stderr)
+        print(f"bench.py measures one GPU (--gpus {args.gpus} requested): the path shards by client, one GPU "
+              "per shard, and multi-GPU runs are not part of this benchmark", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -68,6 +71,13 @@ def main():
     from paper_2406_06963_amd import workloads as wl
 
     dev = "cuda"
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     pr = wl.preset(args.preset)
     W, H = pr.W, pr.H
     HW = W * H

@@ -108,13 +108,37 @@ __device__ __forceinline__ float3 safe_inv(float3 d) {
               1.0f / (fabsf(d.z) > e ? d.z : copysignf(e, d.z)));
 }
 
+// A node: the two child boxes (x and y slabs of child 0, of child 1, then the
+// z slabs of both) and the two child references.
+struct NodeRec {
+    float4 a, b, c, ch;
+};
+
+__device__ __forceinline__ NodeRec load_node(const float4* __restrict__ nodes, int node) {
+    return NodeRec{nodes[4 * node + 0], nodes[4 * node + 1], nodes[4 * node + 2], nodes[4 * node + 3]};
+}
+
+// The same record read at a wave-uniform index through the constant address
+// space (the tree is read-only while kernels run), so it is one scalar load
+// per wave instead of a vector load per lane.
+typedef float vf4 __attribute__((ext_vector_type(4)));
+using cvf4 = const __attribute__((address_space(4))) vf4;
+
+__device__ __forceinline__ float4 ld_const(const float4* base, int i) {
+    const vf4 v = ((cvf4*)base)[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ NodeRec load_node_uniform(const float4* __restrict__ nodes, int node) {
+    return NodeRec{ld_const(nodes, 4 * node), ld_const(nodes, 4 * node + 1), ld_const(nodes, 4 * node + 2),
+                   ld_const(nodes, 4 * node + 3)};
+}
+
 // Slab test of both child boxes of a node against [0, tmax].
-__device__ __forceinline__ void node_test(const float4* __restrict__ nodes, int node, float3 id, float3 ood,
-                                          float tmax, bool& h0, bool& h1, float& tn0, float& tn1, int& c0, int& c1) {
-    const float4 a = nodes[4 * node + 0];
-    const float4 b = nodes[4 * node + 1];
-    const float4 c = nodes[4 * node + 2];
-    const int4 ch = __builtin_bit_cast(int4, nodes[4 * node + 3]);
+__device__ __forceinline__ void box_test(const NodeRec& n, float3 id, float3 ood, float tmax, bool& h0, bool& h1,
+                                         float& tn0, float& tn1, int& c0, int& c1) {
+    const float4 a = n.a, b = n.b, c = n.c;
+    const int4 ch = __builtin_bit_cast(int4, n.ch);
     const float ax0 = fmaf(a.x, id.x, -ood.x), ax1 = fmaf(a.y, id.x, -ood.x);
     const float ay0 = fmaf(a.z, id.y, -ood.y), ay1 = fmaf(a.w, id.y, -ood.y);
     const float az0 = fmaf(c.x, id.z, -ood.z), az1 = fmaf(c.y, id.z, -ood.z);
@@ -133,12 +157,14 @@ __device__ __forceinline__ void node_test(const float4* __restrict__ nodes, int 
     c1 = ch.y;
 }
 
-// Moller-Trumbore in fp32 (two-sided, edges inclusive); returns t or NaN/inf
-// outside.
-__device__ __forceinline__ float tri_t(const float4* __restrict__ tris, int i, float3 o, float3 d) {
-    const float4 v0 = tris[3 * i + 0];
-    const float4 e1 = tris[3 * i + 1];
-    const float4 e2 = tris[3 * i + 2];
+__device__ __forceinline__ void node_test(const float4* __restrict__ nodes, int node, float3 id, float3 ood,
+                                          float tmax, bool& h0, bool& h1, float& tn0, float& tn1, int& c0, int& c1) {
+    box_test(load_node(nodes, node), id, ood, tmax, h0, h1, tn0, tn1, c0, c1);
+}
+
+// Moller-Trumbore in fp32 (two-sided, edges inclusive) of the triangle
+// (v0, e1, e2); returns t or NaN/inf outside.
+__device__ __forceinline__ float tri_t_rec(float4 v0, float4 e1, float4 e2, float3 o, float3 d) {
     const float3 E1 = f3(e1), E2 = f3(e2);
     const float3 p = cross3(d, E2);
     const float det = dot3(E1, p);
@@ -152,6 +178,18 @@ __device__ __forceinline__ float tri_t(const float4* __restrict__ tris, int i, f
     return inside ? t : __builtin_nanf("");
 }
 
+__device__ __forceinline__ float tri_t(const float4* __restrict__ tris, int i, float3 o, float3 d) {
+    return tri_t_rec(tris[3 * i + 0], tris[3 * i + 1], tris[3 * i + 2], o, d);
+}
+
+// Triangle i read at a wave-uniform index (scalar loads).
+__device__ __forceinline__ float tri_t_uniform(const float4* __restrict__ tris, int i, float3 o, float3 d,
+                                               uint32_t* orig = nullptr) {
+    const float4 v0 = ld_const(tris, 3 * i);
+    if (orig) *orig = fbits(v0.w);
+    return tri_t_rec(v0, ld_const(tris, 3 * i + 1), ld_const(tris, 3 * i + 2), o, d);
+}
+
 __device__ __forceinline__ void leaf_range(int ref, int& first, int& count) {
     const int l = ~ref;
     first = l >> 3;
@@ -163,114 +201,124 @@ struct TravCount {
     uint32_t nodes = 0, leaves = 0, tris = 0;
 };
 
-// Traversal in the while-while form with leaf postponing: a lane that reaches
-// a leaf keeps it aside and goes on descending, and the wave only switches to
-// triangle tests once every lane holds a leaf (or has nothing left), so the
-// two kinds of work do not interleave within a wave.  The stack lives in LDS
-// (`stk`: this lane's column, row stride `stride`); the builder caps the depth
-// at kStack, and at most one entry is pushed per interior node on the path.
 constexpr int kDone = 0x7FFFFFFF;  // empty stack
 
-// Any hit at 0 < t < tmax.  With COUNT the lane's work is tallied in `cnt`.
-template <bool COUNT = false>
-__device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const float4* __restrict__ tris,
-                                        const Ray& r, int* stk, int stride, TravCount* cnt = nullptr) {
-    const float3 id = safe_inv(r.d);
-    const float3 ood = f3(r.o.x * id.x, r.o.y * id.y, r.o.z * id.z);
-    int sp = 0;
-    int node = 0;   // interior index >= 0, leaf ref < 0, kDone
-    int leaf = 0;   // postponed leaf ref (< 0) or none (>= 0)
-    while (node != kDone || leaf < 0) {
-        while (node >= 0 && node != kDone) {
+// ---------------------------------------------------------------- traversal
+// The whole wave walks one path through the tree: the union of its lanes'
+// paths (rays of a wave come from an 8 x 8 pixel square, so they share most
+// of it).  A child is entered when any lane's ray hits its box, the nearer
+// child first by majority vote of the lanes that hit both.  Node and
+// triangle records are read once per wave at a uniform address (scalar
+// loads), and the stack is one LDS column per wave (`wstk`,
+// kStack entries: the builder caps the depth at kStack and at most one entry
+// is pushed per level).  Child boxes lie inside the parent's box and the slab
+// test is monotone in the planes, so a lane visits every node its own ray
+// hits: each lane's result is that of a traversal of its own ray.  Lanes
+// without work pass tmax < 0, which misses every box.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// visit_leaf(first, count) tests a leaf's triangles for every lane; done()
+// is true once no lane needs more of the walk; tmax is read at every node.
+// With COUNT, `cnt` tallies the work of this lane's own ray: the nodes and
+// leaves whose boxes it hits (a bit stack beside the wave's stack records
+// whether it hit each pushed child) and the triangles of those leaves.
+template <bool COUNT, class Leaf, class Done>
+__device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, float3 id, float3 ood,
+                                            const float& tmax, bool live, int* wstk, Leaf visit_leaf, Done done,
+                                            TravCount* cnt) {
+    int sp = 0, node = 0;
+    bool in = live;          // COUNT: this lane's ray hits the current node
+    uint32_t in_stack = 0;   // COUNT: the same for every stack entry
+    while (true) {
+        if (node >= 0) {
             bool h0, h1;
             float t0, t1;
             int c0, c1;
-            if (COUNT) ++cnt->nodes;
-            node_test(nodes, node, id, ood, r.tmax, h0, h1, t0, t1, c0, c1);
-            if (h0 && h1) {
-                const bool first0 = t0 <= t1;
-                stk[sp * stride] = first0 ? c1 : c0;
-                ++sp;
+            if (COUNT && in) ++cnt->nodes;
+            box_test(load_node_uniform(nodes, node), id, ood, tmax, h0, h1, t0, t1, c0, c1);
+            c0 = uniform(c0);
+            c1 = uniform(c1);
+            const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
+            if (m0 && m1) {
+                const uint64_t f0 = __ballot(h0 && h1 && t0 <= t1);
+                const bool first0 = 2 * __popcll(f0) >= __popcll(m0 & m1);
+                if (COUNT) {
+                    in_stack = (in_stack & ~(1u << sp)) | ((first0 ? h1 : h0) ? 1u << sp : 0u);
+                    in = first0 ? h0 : h1;
+                }
+                wstk[sp++] = first0 ? c1 : c0;
                 node = first0 ? c0 : c1;
-            } else if (h0 || h1) {
-                node = h0 ? c0 : c1;
-            } else {
-                node = sp ? stk[--sp * stride] : kDone;
+                continue;
             }
-            if (node < 0 && leaf >= 0) {
-                leaf = node;
-                node = sp ? stk[--sp * stride] : kDone;
+            if (m0 | m1) {
+                if (COUNT) in = m0 ? h0 : h1;
+                node = m0 ? c0 : c1;
+                continue;
             }
-            if (!__any(leaf >= 0)) break;
-        }
-        while (leaf < 0) {
+        } else {
             int first, count;
-            leaf_range(leaf, first, count);
-            if (COUNT) ++cnt->leaves;
-            for (int k = 0; k < count; ++k) {
-                if (COUNT) ++cnt->tris;
-                const float t = tri_t(tris, first + k, r.o, r.d);
-                if (t > 0.0f && t < r.tmax) return true;
+            leaf_range(node, first, count);
+            if (COUNT && in) {
+                ++cnt->leaves;
+                cnt->tris += count;
             }
-            leaf = node;
-            if (node < 0) node = sp ? stk[--sp * stride] : kDone;
+            visit_leaf(first, count);
+            if (done()) return;
         }
+        if (sp == 0) return;
+        node = uniform(wstk[--sp]);
+        if (COUNT) in = (in_stack >> sp) & 1u;
     }
-    return false;
 }
 
-// Closest hit at t > 0 (ties: lowest original triangle index).  Returns the
-// position of the triangle in leaf order, or -1.
-__device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, const float4* __restrict__ tris,
-                                           float3 o, float3 d, float& tbest, int* stk, int stride) {
-    const float3 id = safe_inv(d);
-    const float3 ood = f3(o.x * id.x, o.y * id.y, o.z * id.z);
-    int sp = 0;
-    int node = 0;
-    int leaf = 0;
-    int best = -1;
-    uint32_t best_orig = 0xFFFFFFFFu;
-    tbest = __builtin_inff();
-    while (node != kDone || leaf < 0) {
-        while (node >= 0 && node != kDone) {
-            bool h0, h1;
-            float t0, t1;
-            int c0, c1;
-            node_test(nodes, node, id, ood, tbest, h0, h1, t0, t1, c0, c1);
-            if (h0 && h1) {
-                const bool first0 = t0 <= t1;
-                stk[sp * stride] = first0 ? c1 : c0;
-                ++sp;
-                node = first0 ? c0 : c1;
-            } else if (h0 || h1) {
-                node = h0 ? c0 : c1;
-            } else {
-                node = sp ? stk[--sp * stride] : kDone;
-            }
-            if (node < 0 && leaf >= 0) {
-                leaf = node;
-                node = sp ? stk[--sp * stride] : kDone;
-            }
-            if (!__any(leaf >= 0)) break;
-        }
-        while (leaf < 0) {
-            int first, count;
-            leaf_range(leaf, first, count);
+// Any hit at 0 < t < r.tmax for the lanes with `live`; the others return false.
+template <bool COUNT = false>
+__device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const float4* __restrict__ tris, const Ray& r,
+                                        bool live, int* wstk, TravCount* cnt = nullptr) {
+    if (!__any(live)) return false;
+    const float3 id = safe_inv(r.d);
+    const float3 ood = f3(r.o.x * id.x, r.o.y * id.y, r.o.z * id.z);
+    float tmax = live ? r.tmax : -1.0f;
+    bool hit = false;
+    packet_walk<COUNT>(
+        nodes, id, ood, tmax, live, wstk,
+        [&](int first, int count) {
             for (int k = 0; k < count; ++k) {
-                const float t = tri_t(tris, first + k, o, d);
-                if (t > 0.0f && t <= tbest) {
-                    const uint32_t orig = fbits(tris[3 * (first + k)].w);
-                    if (t < tbest || orig < best_orig) {
-                        tbest = t;
-                        best = first + k;
-                        best_orig = orig;
-                    }
+                const float t = tri_t_uniform(tris, first + k, r.o, r.d);
+                if (t > 0.0f && t < tmax) {  // false for finished lanes (tmax < 0)
+                    hit = true;
+                    tmax = -1.0f;
                 }
             }
-            leaf = node;
-            if (node < 0) node = sp ? stk[--sp * stride] : kDone;
-        }
-    }
+        },
+        [&] { return !__any(tmax >= 0.0f); }, cnt);
+    return hit;
+}
+
+// Closest hit at t > 0 (ties: lowest original triangle index) for the lanes
+// with `live`; returns the position in leaf order, or -1.
+__device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, const float4* __restrict__ tris, float3 o,
+                                           float3 d, bool live, float& tbest, int* wstk) {
+    const float3 id = safe_inv(d);
+    const float3 ood = f3(o.x * id.x, o.y * id.y, o.z * id.z);
+    int best = -1;
+    uint32_t best_orig = 0xFFFFFFFFu;
+    tbest = live ? __builtin_inff() : -1.0f;
+    packet_walk<false>(
+        nodes, id, ood, tbest, live, wstk,
+        [&](int first, int count) {
+            for (int k = 0; k < count; ++k) {
+                uint32_t orig;
+                const float t = tri_t_uniform(tris, first + k, o, d, &orig);
+                if (t > 0.0f && t <= tbest && (t < tbest || orig < best_orig)) {
+                    tbest = t;
+                    best = first + k;
+                    best_orig = orig;
+                }
+            }
+        },
+        [] { return false; }, nullptr);
+    if (!live) tbest = __builtin_inff();
     return best;
 }
 

@@ -2,10 +2,9 @@
 // rays (ambient occlusion, Section 3.2; soft shadows, Section 3.1).
 //
 // Layout: one lane per pixel; a 128-lane workgroup covers a 16 x 8 tile and
-// each 64-lane wave an 8 x 8 square (coherent rays).  The traversal stack of
-// every lane lives in LDS (32 entries, interleaved by lane so consecutive
-// lanes hit consecutive banks).  Jobs of a ragged batch are passed by value
-// in the kernel arguments.
+// each 64-lane wave an 8 x 8 square, whose rays traverse the tree together
+// (one walk per wave, the stack one LDS column per wave).  Jobs of a ragged
+// batch are passed by value in the kernel arguments.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -78,7 +77,7 @@ __device__ __forceinline__ float3 cam_dir(const CamD& c, float px, float py, uin
 // visits and triangle tests into `counters` (device uint64[4]).
 template <bool COUNT>
 __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsigned long long* counters) {
-    __shared__ int stack[kStack * kBlock];
+    __shared__ int stack[kStack * (kBlock / 64)];
     const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
     const TraceDesc& D = B.d[j];
     uint32_t x, y;
@@ -94,23 +93,23 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsig
     float eps = D.eps_abs;
     if (!(eps > 0.0f)) eps = fmaxf(1e-3f * D.ao_r, fmaxf(fmaxf(fabsf(p.x), fabsf(p.y)), fabsf(p.z)) * 0x1p-17f);
     const float3 o = p + n * eps;
-    int* stk = stack + threadIdx.x;
     TravCount tc;
     uint32_t n_rays = 0;
 
+    int* wstk = stack + (threadIdx.x >> 6) * kStack;
     for (uint32_t st = 0; st <= D.n_lights; ++st) {
         const uint32_t nr = st == 0 ? D.n_ao : D.n_shadow;
         uint32_t cnt = 0;
         uint64_t bits = 0;
-        if (!valid) {
-            cnt = nr;
-            bits = nr >= 64 ? ~0ull : ((1ull << nr) - 1ull);
-        } else {
-            for (uint32_t s = 0; s < nr; ++s) {
+        for (uint32_t s = 0; s < nr; ++s) {
+            bool occ = true;   // invalid pixels count every ray as unoccluded below
+            bool decided = !valid;
+            Ray r;
+            r.o = o;
+            r.d = n;
+            r.tmax = 0.0f;
+            if (valid) {
                 const float2 u = ray_uniforms(D.seed, D.client, x, y, D.frame, st, st == 0 ? D.ao_off + s : s);
-                Ray r;
-                r.o = o;
-                bool decided = false, occ = false;
                 if (st == 0) {
                     r.d = sample_cosine(n, u.x, u.y);
                     r.tmax = D.ao_r;
@@ -141,14 +140,13 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsig
                         occ = true;
                     }
                 }
-                if (!decided) {
-                    occ = any_hit<COUNT>(D.nodes, D.tris, r, stk, kBlock, &tc);
-                    if (COUNT) ++n_rays;
-                }
-                if (!occ) {
-                    ++cnt;
-                    if (s < 64) bits |= 1ull << s;
-                }
+            }
+            const bool h = any_hit<COUNT>(D.nodes, D.tris, r, !decided, wstk, &tc);
+            if (!decided) occ = h;
+            if (COUNT && !decided) ++n_rays;
+            if (!valid || !occ) {
+                ++cnt;
+                if (s < 64) bits |= 1ull << s;
             }
         }
         if (st == 0)
@@ -167,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsig
 }
 
 __global__ __launch_bounds__(kBlock) void gbuffer_kernel(const GbufBatch B) {
-    __shared__ int stack[kStack * kBlock];
+    __shared__ int stack[kStack * (kBlock / 64)];
     const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
     const GbufDesc& D = B.d[j];
     uint32_t x, y;
@@ -179,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void gbuffer_kernel(const GbufBatch B) {
     const float3 fwd = f3(C.fwd[0], C.fwd[1], C.fwd[2]);
     const float3 d = cam_dir(C, x + 0.5f, y + 0.5f, D.W, D.H);
     float t;
-    const int hit = closest_hit(D.nodes, D.tris, eye, d, t, stack + threadIdx.x, kBlock);
+    const int hit = closest_hit(D.nodes, D.tris, eye, d, true, t, stack + (threadIdx.x >> 6) * kStack);
     if (hit < 0) {
         D.pos[i] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(DHR_MISS_ID));
         D.nz[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
