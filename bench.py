@@ -27,7 +27,43 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # fp32 operations per traversal step, counted from the kernel source
 FLOPS_PER_NODE = 50      # two slab tests: 12 FMA (24) + 24 min/max + 2 compares
-FLOPS_PER_TRI = 51       # Moller-Trumbore: 2 cross, 4 dot, reciprocal, 3 scalings, 7 compares/adds
+FLOPS_PER_TRI = 48       # Moller-Trumbore without division: 2 cross (18), 4 dot (20), o - v0 (3),
+                         # u + v and tmax |det| (2), 5 compares
+
+# Hardware byte counters of the dominant kernels, per launch, from the
+# committed rocprofv3 --pmc summary; each entry holds the SHA-256 of the
+# kernel's sources when it was taken and is ignored once they change.
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_terrain1080.md")
+KERNEL_SOURCES = {
+    "trace_kernel": ["trace.hip", "device.h"],
+    "gbuffer_kernel": ["trace.hip", "device.h"],
+    "svgf_pass": ["svgf.hip", "svgf_common.h", "device.h"],
+}
+
+
+def sources_sha(kernel: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2406_06963_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_traffic(kernel: str):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the
+    committed summary, or None if absent or taken on other sources."""
+    try:
+        with open(PMC_SUMMARY) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    sha = sources_sha(kernel)
+    for ln in lines:
+        f = ln.split()
+        if len(f) == 4 and f[0] == "traffic:" and f[1] == kernel and f[2] == sha:
+            return float(f[3])
+    return None
 
 
 def parse():
@@ -161,7 +197,7 @@ def main():
     svgf_s = per["svgf"] / 1e3
     svgf_bytes = svgf_bytes_per_px(pr.levels) * HW
     roof_svgf = {"bound": "hbm", "achieved": svgf_bytes / svgf_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": svgf_bytes / svgf_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                 "frac": svgf_bytes / svgf_s / 1e9 / HBM_PEAK_GBS, "traffic": pmc_traffic("svgf_pass"),
                  "kernel": "svgf (temporal + variance + 5 a-trous levels)",
                  "algorithmic_bytes_per_px": svgf_bytes_per_px(pr.levels)}
     roof_trace = None
@@ -169,7 +205,8 @@ def main():
         flops = counts[1] * FLOPS_PER_NODE + counts[3] * FLOPS_PER_TRI
         ach = flops / trace_s / 1e12
         roof_trace = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                      "frac": ach / VALU_PEAK_TFLOPS, "traffic": None, "kernel": "trace_visibility",
+                      "frac": ach / VALU_PEAK_TFLOPS, "traffic": pmc_traffic("trace_kernel"),
+                      "kernel": "trace_visibility",
                       "traced_rays": counts[0], "node_visits": counts[1], "leaf_visits": counts[2],
                       "tri_tests": counts[3], "flops_per_node": FLOPS_PER_NODE, "flops_per_tri": FLOPS_PER_TRI}
     dominant = "trace" if per["trace"] >= per["svgf"] else "svgf"

@@ -114,13 +114,9 @@ struct NodeRec {
     float4 a, b, c, ch;
 };
 
-__device__ __forceinline__ NodeRec load_node(const float4* __restrict__ nodes, int node) {
-    return NodeRec{nodes[4 * node + 0], nodes[4 * node + 1], nodes[4 * node + 2], nodes[4 * node + 3]};
-}
-
-// The same record read at a wave-uniform index through the constant address
-// space (the tree is read-only while kernels run), so it is one scalar load
-// per wave instead of a vector load per lane.
+// Records are read at wave-uniform indices through the constant address
+// space (the tree is read-only while kernels run): one scalar load per wave
+// instead of a vector load per lane.
 typedef float vf4 __attribute__((ext_vector_type(4)));
 using cvf4 = const __attribute__((address_space(4))) vf4;
 
@@ -134,32 +130,46 @@ __device__ __forceinline__ NodeRec load_node_uniform(const float4* __restrict__ 
                    ld_const(nodes, 4 * node + 3)};
 }
 
-// Slab test of both child boxes of a node against [0, tmax].
-__device__ __forceinline__ void box_test(const NodeRec& n, float3 id, float3 ood, float tmax, bool& h0, bool& h1,
-                                         float& tn0, float& tn1, int& c0, int& c1) {
+// Slab test of both child boxes of a node against [0, tmax].  With OCT the
+// sign of every lane's inverse direction on each axis is the same (sx, sy, sz
+// true for negative): the entry and exit planes are then picked once per
+// wave instead of by a min and a max per lane.  Both forms give the same
+// result, since fma rounding is monotone in the plane coordinate.
+template <bool OCT>
+__device__ __forceinline__ void box_test(const NodeRec& n, bool sx, bool sy, bool sz, float3 id, float3 ood,
+                                         float tmax, bool& h0, bool& h1, float& tn0, float& tn1, int& c0, int& c1) {
     const float4 a = n.a, b = n.b, c = n.c;
     const int4 ch = __builtin_bit_cast(int4, n.ch);
-    const float ax0 = fmaf(a.x, id.x, -ood.x), ax1 = fmaf(a.y, id.x, -ood.x);
-    const float ay0 = fmaf(a.z, id.y, -ood.y), ay1 = fmaf(a.w, id.y, -ood.y);
-    const float az0 = fmaf(c.x, id.z, -ood.z), az1 = fmaf(c.y, id.z, -ood.z);
-    const float bx0 = fmaf(b.x, id.x, -ood.x), bx1 = fmaf(b.y, id.x, -ood.x);
-    const float by0 = fmaf(b.z, id.y, -ood.y), by1 = fmaf(b.w, id.y, -ood.y);
-    const float bz0 = fmaf(c.z, id.z, -ood.z), bz1 = fmaf(c.w, id.z, -ood.z);
-    const float a_in = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
-    const float a_out = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tmax));
-    const float b_in = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
-    const float b_out = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tmax));
+    float a_in, a_out, b_in, b_out;
+    if (OCT) {
+        const float anx = fmaf(sx ? a.y : a.x, id.x, -ood.x), afx = fmaf(sx ? a.x : a.y, id.x, -ood.x);
+        const float any = fmaf(sy ? a.w : a.z, id.y, -ood.y), afy = fmaf(sy ? a.z : a.w, id.y, -ood.y);
+        const float anz = fmaf(sz ? c.y : c.x, id.z, -ood.z), afz = fmaf(sz ? c.x : c.y, id.z, -ood.z);
+        const float bnx = fmaf(sx ? b.y : b.x, id.x, -ood.x), bfx = fmaf(sx ? b.x : b.y, id.x, -ood.x);
+        const float bny = fmaf(sy ? b.w : b.z, id.y, -ood.y), bfy = fmaf(sy ? b.z : b.w, id.y, -ood.y);
+        const float bnz = fmaf(sz ? c.w : c.z, id.z, -ood.z), bfz = fmaf(sz ? c.z : c.w, id.z, -ood.z);
+        a_in = fmaxf(fmaxf(anx, any), fmaxf(anz, 0.0f));
+        a_out = fminf(fminf(afx, afy), fminf(afz, tmax));
+        b_in = fmaxf(fmaxf(bnx, bny), fmaxf(bnz, 0.0f));
+        b_out = fminf(fminf(bfx, bfy), fminf(bfz, tmax));
+    } else {
+        const float ax0 = fmaf(a.x, id.x, -ood.x), ax1 = fmaf(a.y, id.x, -ood.x);
+        const float ay0 = fmaf(a.z, id.y, -ood.y), ay1 = fmaf(a.w, id.y, -ood.y);
+        const float az0 = fmaf(c.x, id.z, -ood.z), az1 = fmaf(c.y, id.z, -ood.z);
+        const float bx0 = fmaf(b.x, id.x, -ood.x), bx1 = fmaf(b.y, id.x, -ood.x);
+        const float by0 = fmaf(b.z, id.y, -ood.y), by1 = fmaf(b.w, id.y, -ood.y);
+        const float bz0 = fmaf(c.z, id.z, -ood.z), bz1 = fmaf(c.w, id.z, -ood.z);
+        a_in = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
+        a_out = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tmax));
+        b_in = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
+        b_out = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tmax));
+    }
     h0 = a_in <= a_out;
     h1 = b_in <= b_out;
     tn0 = a_in;
     tn1 = b_in;
     c0 = ch.x;
     c1 = ch.y;
-}
-
-__device__ __forceinline__ void node_test(const float4* __restrict__ nodes, int node, float3 id, float3 ood,
-                                          float tmax, bool& h0, bool& h1, float& tn0, float& tn1, int& c0, int& c1) {
-    box_test(load_node(nodes, node), id, ood, tmax, h0, h1, tn0, tn1, c0, c1);
 }
 
 // Moller-Trumbore in fp32 (two-sided, edges inclusive) of the triangle
@@ -178,16 +188,31 @@ __device__ __forceinline__ float tri_t_rec(float4 v0, float4 e1, float4 e2, floa
     return inside ? t : __builtin_nanf("");
 }
 
-__device__ __forceinline__ float tri_t(const float4* __restrict__ tris, int i, float3 o, float3 d) {
-    return tri_t_rec(tris[3 * i + 0], tris[3 * i + 1], tris[3 * i + 2], o, d);
-}
-
 // Triangle i read at a wave-uniform index (scalar loads).
 __device__ __forceinline__ float tri_t_uniform(const float4* __restrict__ tris, int i, float3 o, float3 d,
                                                uint32_t* orig = nullptr) {
     const float4 v0 = ld_const(tris, 3 * i);
     if (orig) *orig = fbits(v0.w);
     return tri_t_rec(v0, ld_const(tris, 3 * i + 1), ld_const(tris, 3 * i + 2), o, d);
+}
+
+// Whether the ray hits triangle i at 0 < t < tmax: the Moller-Trumbore
+// tests with the barycentrics and t left unnormalised (multiplied by det,
+// signed by det), so no division is needed.
+__device__ __forceinline__ bool tri_hits_uniform(const float4* __restrict__ tris, int i, float3 o, float3 d,
+                                                 float tmax) {
+    const float4 v0 = ld_const(tris, 3 * i), e1 = ld_const(tris, 3 * i + 1), e2 = ld_const(tris, 3 * i + 2);
+    const float3 E1 = f3(e1), E2 = f3(e2);
+    const float3 p = cross3(d, E2);
+    const float det = dot3(E1, p);
+    const float3 tv = o - f3(v0);
+    const float3 q = cross3(tv, E1);
+    const uint32_t sgn = fbits(det) & 0x80000000u;
+    const float U = __uint_as_float(fbits(dot3(tv, p)) ^ sgn);
+    const float V = __uint_as_float(fbits(dot3(d, q)) ^ sgn);
+    const float T = __uint_as_float(fbits(dot3(E2, q)) ^ sgn);
+    const float ad = fabsf(det);
+    return (U >= 0.0f) & (V >= 0.0f) & (U + V <= ad) & (T > 0.0f) & (T < tmax * ad);
 }
 
 __device__ __forceinline__ void leaf_range(int ref, int& first, int& count) {
@@ -222,10 +247,14 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // With COUNT, `cnt` tallies the work of this lane's own ray: the nodes and
 // leaves whose boxes it hits (a bit stack beside the wave's stack records
 // whether it hit each pushed child) and the triangles of those leaves.
-template <bool COUNT, class Leaf, class Done>
+template <bool COUNT, bool OCT, class Leaf, class Done>
 __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, float3 id, float3 ood,
                                             const float& tmax, bool live, int* wstk, Leaf visit_leaf, Done done,
                                             TravCount* cnt) {
+    // octant of the live lanes (used with OCT, where it is the same for all)
+    const bool sx = __ballot(live && id.x < 0.0f) != 0;
+    const bool sy = __ballot(live && id.y < 0.0f) != 0;
+    const bool sz = __ballot(live && id.z < 0.0f) != 0;
     int sp = 0, node = 0;
     bool in = live;          // COUNT: this lane's ray hits the current node
     uint32_t in_stack = 0;   // COUNT: the same for every stack entry
@@ -235,7 +264,7 @@ __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, fl
             float t0, t1;
             int c0, c1;
             if (COUNT && in) ++cnt->nodes;
-            box_test(load_node_uniform(nodes, node), id, ood, tmax, h0, h1, t0, t1, c0, c1);
+            box_test<OCT>(load_node_uniform(nodes, node), sx, sy, sz, id, ood, tmax, h0, h1, t0, t1, c0, c1);
             c0 = uniform(c0);
             c1 = uniform(c1);
             const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
@@ -271,6 +300,14 @@ __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, fl
     }
 }
 
+// True when the live lanes' inverse directions share one octant.
+__device__ __forceinline__ bool same_octant(float3 id, bool live) {
+    const uint64_t m = __ballot(live);
+    const uint64_t x = __ballot(live && id.x < 0.0f), y = __ballot(live && id.y < 0.0f),
+                   z = __ballot(live && id.z < 0.0f);
+    return (x == 0 || x == m) && (y == 0 || y == m) && (z == 0 || z == m);
+}
+
 // Any hit at 0 < t < r.tmax for the lanes with `live`; the others return false.
 template <bool COUNT = false>
 __device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const float4* __restrict__ tris, const Ray& r,
@@ -280,18 +317,19 @@ __device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const 
     const float3 ood = f3(r.o.x * id.x, r.o.y * id.y, r.o.z * id.z);
     float tmax = live ? r.tmax : -1.0f;
     bool hit = false;
-    packet_walk<COUNT>(
-        nodes, id, ood, tmax, live, wstk,
-        [&](int first, int count) {
-            for (int k = 0; k < count; ++k) {
-                const float t = tri_t_uniform(tris, first + k, r.o, r.d);
-                if (t > 0.0f && t < tmax) {  // false for finished lanes (tmax < 0)
-                    hit = true;
-                    tmax = -1.0f;
-                }
+    auto leaf = [&](int first, int count) {
+        for (int k = 0; k < count; ++k) {
+            if (tri_hits_uniform(tris, first + k, r.o, r.d, tmax)) {  // false for finished lanes (tmax < 0)
+                hit = true;
+                tmax = -1.0f;
             }
-        },
-        [&] { return !__any(tmax >= 0.0f); }, cnt);
+        }
+    };
+    auto done = [&] { return !__any(tmax >= 0.0f); };
+    if (same_octant(id, live))
+        packet_walk<COUNT, true>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt);
+    else
+        packet_walk<COUNT, false>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt);
     return hit;
 }
 
@@ -304,20 +342,22 @@ __device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, con
     int best = -1;
     uint32_t best_orig = 0xFFFFFFFFu;
     tbest = live ? __builtin_inff() : -1.0f;
-    packet_walk<false>(
-        nodes, id, ood, tbest, live, wstk,
-        [&](int first, int count) {
-            for (int k = 0; k < count; ++k) {
-                uint32_t orig;
-                const float t = tri_t_uniform(tris, first + k, o, d, &orig);
-                if (t > 0.0f && t <= tbest && (t < tbest || orig < best_orig)) {
-                    tbest = t;
-                    best = first + k;
-                    best_orig = orig;
-                }
+    auto leaf = [&](int first, int count) {
+        for (int k = 0; k < count; ++k) {
+            uint32_t orig;
+            const float t = tri_t_uniform(tris, first + k, o, d, &orig);
+            if (t > 0.0f && t <= tbest && (t < tbest || orig < best_orig)) {
+                tbest = t;
+                best = first + k;
+                best_orig = orig;
             }
-        },
-        [] { return false; }, nullptr);
+        }
+    };
+    auto done = [] { return false; };
+    if (same_octant(id, live))
+        packet_walk<false, true>(nodes, id, ood, tbest, live, wstk, leaf, done, nullptr);
+    else
+        packet_walk<false, false>(nodes, id, ood, tbest, live, wstk, leaf, done, nullptr);
     if (!live) tbest = __builtin_inff();
     return best;
 }

@@ -398,12 +398,6 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, c
 // 64 + 4s consecutive pixels.  Staging reads whole row segments (coalesced at
 // any stride) and each staged pixel serves up to 20 taps from LDS.  Tile t of
 // a frame: column block t % tx, then row class, then block of 4s rows.
-constexpr int kRowsTX = 64, kRowsTY = kSvgfBlock / kRowsTX;
-
-__host__ __device__ constexpr uint32_t rows_tiles(uint32_t W, uint32_t H, int level) {
-    return ((W + kRowsTX - 1) / kRowsTX) * (1u << level) * ((H + (kRowsTY << level) - 1) / (kRowsTY << level));
-}
-
 template <int LEVEL>
 __global__ __launch_bounds__(kSvgfBlock) void atrous_rows_kernel(const SvgfBatch B, const SvgfK P) {
     constexpr int s = 1 << LEVEL;
@@ -631,10 +625,11 @@ uint64_t dhr_svgf_workspace_bytes(uint32_t W, uint32_t H, const dhr_svgf_params*
     const uint32_t L = params ? params->levels : 5;
     if (which == 0) return 2 * HW * 8 + HW * 4;   // (c, var) ping-pong + ke
     // adjoint: per-pixel coefficients (float4), two (c, v) adjoint buffers,
-    // prefilter/centre terms (float4), and per-tile sigma partials (3 doubles
-    // per level and tile)
-    const uint64_t tiles = (uint64_t)((W + dhr::kSvgfTile - 1) / dhr::kSvgfTile) * ((H + dhr::kSvgfTile - 1) / dhr::kSvgfTile);
-    return HW * 16 + 2 * HW * 8 + HW * 16 + (uint64_t)L * tiles * 24;
+    // prefilter/centre terms (float4), and per-workgroup sigma partials (3
+    // doubles per level and workgroup)
+    uint64_t tiles = 0;
+    for (uint32_t l = 0; l < L && l < DHR_MAX_LEVELS; ++l) tiles += dhr::adjoint_tiles(W, H, l);
+    return HW * 16 + 2 * HW * 8 + HW * 16 + tiles * 24;
 }
 
 dhr_status dhr_svgf_filter(dhr_ctx* ctx, const dhr_svgf_params* params, const dhr_svgf_frame* frames,

@@ -35,7 +35,8 @@ struct BwdDesc {
     float2* g1;
     float4* coef;           // [HW] (A, B, c', E)
     float4* aux;            // [HW] (prefilter adjoint / sk, centre-role dc, K, 0)
-    double* part;           // [levels][tiles][3]
+    double* part;           // [sum over levels of the level's workgroups][3]
+    uint32_t part_off[DHR_MAX_LEVELS + 1];  // first workgroup of each level in part
 };
 constexpr int kBwdMaxB = 24;
 using BwdBatch = Batch<BwdDesc, kBwdMaxB>;
@@ -59,7 +60,8 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return s;
 }
 
-__global__ __launch_bounds__(kSvgfBlock) void adjoint_a_kernel(const BwdBatch Bt, const SvgfK P, uint32_t level) {
+// Pass A on 16 x 16 tiles with taps read from global memory (deep levels).
+__global__ __launch_bounds__(kSvgfBlock) void adjoint_a_direct(const BwdBatch Bt, const SvgfK P, uint32_t level) {
     __shared__ double red[kSvgfBlock / 64];
     const int j = find_job(Bt.tile0, (int)Bt.n, blockIdx.x);
     const BwdDesc& D = Bt.d[j];
@@ -167,14 +169,15 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_a_kernel(const BwdBatch Bt
     const double tn = block_sum((double)s_n, red);
     const double tl = block_sum((double)s_l, red);
     if (threadIdx.x == 0) {
-        double* o = D.part + ((size_t)level * D.tiles + tile) * 3;
+        double* o = D.part + ((size_t)D.part_off[level] + tile) * 3;
         o[0] = tz;
         o[1] = tn;
         o[2] = tl;
     }
 }
 
-__global__ __launch_bounds__(kSvgfBlock) void adjoint_b_kernel(const BwdBatch Bt, const SvgfK P, uint32_t level) {
+// Pass B on 16 x 16 tiles with taps read from global memory (deep levels).
+__global__ __launch_bounds__(kSvgfBlock) void adjoint_b_direct(const BwdBatch Bt, const SvgfK P, uint32_t level) {
     const int j = find_job(Bt.tile0, (int)Bt.n, blockIdx.x);
     const BwdDesc& D = Bt.d[j];
     uint32_t x, y;
@@ -236,6 +239,265 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_b_kernel(const BwdBatch Bt
     out[i] = make_float2(acc_c, acc_v);
 }
 
+// The same two passes on row-class tiles (levels up to kAdjRowsMax): the
+// taps' geometry and inputs are staged in LDS once per workgroup, as in the
+// forward levels.  Taps outside the frame or on invalid pixels are staged
+// with a zero normal (their weight is zero) and, in pass B, E = 1 (every
+// term stays finite and vanishes).
+template <int LEVEL>
+__global__ __launch_bounds__(kSvgfBlock) void adjoint_a_rows(const BwdBatch Bt, const SvgfK P) {
+    constexpr int s = 1 << LEVEL;
+    constexpr int CW = kRowsTX + 4 * s, CH = kRowsTY + 4, GW = kRowsTX + 2;
+    __shared__ float4 s_nz[CH * CW];
+    __shared__ float2 s_cv[CH * CW];
+    __shared__ float s_g[kRowsTY * 2 * GW];  // variance of the rows next to each output row
+    __shared__ double red[kSvgfBlock / 64];
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int j = find_job(Bt.tile0, (int)Bt.n, lb);
+    const BwdDesc& D = Bt.d[j];
+    const int t = (int)(lb - Bt.tile0[j]);
+    const int W = (int)D.W, H = (int)D.H;
+    const int ntx = (W + kRowsTX - 1) / kRowsTX;
+    const int X = t % ntx, rest = t / ntx;
+    const int x0 = X * kRowsTX, y0 = (rest / s) * (kRowsTY * s) + rest % s;
+    const float2* cv = D.save + (size_t)LEVEL * W * H;
+    stage_tile<CH * CW>(
+        [&](int e) {
+            const int qx = x0 - 2 * s + e % CW, qy = y0 + s * (e / CW - 2);
+            Staged r{make_float4(0.0f, 0.0f, 0.0f, 0.0f), make_float2(0.0f, 0.0f)};
+            if (qx >= 0 && qx < W && qy >= 0 && qy < H) {
+                const size_t q = (size_t)qy * W + qx;
+                r.nz = D.nz[q];
+                r.cv = cv[q];
+            }
+            return r;
+        },
+        [&](int e, const Staged& r) {
+            const bool ok = r.nz.w > 0.0f;
+            s_nz[e] = ok ? r.nz : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            s_cv[e] = ok ? r.cv : make_float2(0.0f, 0.0f);
+        });
+    stage_tile<kRowsTY * 2 * GW>(
+        [&](int e) {
+            const int qx = x0 - 1 + e % GW, qy = y0 + s * (e / (2 * GW)) + ((e / GW) % 2 ? 1 : -1);
+            float v = kNoVar;
+            if (qx >= 0 && qx < W && qy >= 0 && qy < H) {
+                const size_t q = (size_t)qy * W + qx;
+                const float vq = cv[q].y;
+                if (D.nz[q].w > 0.0f) v = vq;
+            }
+            return v;
+        },
+        [&](int e, float v) { s_g[e] = v; });
+    __syncthreads();
+    const int li = threadIdx.x % kRowsTX, lj = threadIdx.x / kRowsTX;
+    const int x = x0 + li, y = y0 + s * lj;
+    const int c = (lj + 2) * CW + 2 * s + li;
+    float s_z = 0.0f, s_n = 0.0f, s_l = 0.0f;
+    if (x < W && y < H) {
+        const size_t i = (size_t)y * W + x;
+        const float4 n4 = s_nz[c];
+        if (!(n4.w > 0.0f)) {
+            D.coef[i] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+            D.aux[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        } else {
+            const uint32_t L = P.levels;
+            float ab, bb;
+            if (LEVEL + 1 == (int)L) {
+                ab = D.grad_out[i];
+                bb = 0.0f;
+            } else {
+                const float2 g = adj_out(D, LEVEL + 1, L)[i];
+                ab = g.x;
+                bb = g.y;
+            }
+            float G = 0.0f, sk = 0.0f;
+#pragma unroll
+            for (int b = -1; b <= 1; ++b)
+#pragma unroll
+                for (int a = -1; a <= 1; ++a) {
+                    float v;
+                    if (b == 0)
+                        v = s_nz[c + a].w > 0.0f ? s_cv[c + a].y : kNoVar;
+                    else
+                        v = s_g[(2 * lj + (b > 0)) * GW + li + 1 + a];
+                    if (!has_var(v)) continue;
+                    const float k = k3(a) * k3(b);
+                    G = fmaf(k, v, G);
+                    sk += k;
+                }
+            const float g = sqrtf(G / sk);
+            const float sl = P.sl[LEVEL], sz = P.sz[LEVEL], sn = P.sn[LEVEL];
+            const float E = fmaf(sl, g, P.eps_l);
+            const float iE = 1.0f / E;
+            const float ke = kNegLog2e * iE;
+            const float2 cvp = s_cv[c];
+            const float2 dzp = D.dz[i];
+            const float3 np = f3(n4);
+            const float eps_zp = P.eps_z * n4.w;
+            // sweep 1: normaliser and the level's outputs (one tap row per
+            // iteration: unrolling all 25 taps would hoist their LDS reads
+            // and hold them all in registers)
+            float Dn = 0.0f, Sc = 0.0f, Sv = 0.0f;
+#pragma unroll 1
+            for (int b = -2; b <= 2; ++b)
+#pragma unroll
+            for (int a = -2; a <= 2; ++a) {
+                const int e = c + b * CW + s * a;
+                const float4 nq = s_nz[e];
+                const float2 c2 = s_cv[e];
+                const float w = (a == 0 && b == 0)
+                                    ? 1.0f
+                                    : fused_weight(depth_coef(dzp, a, b, s, sz, eps_zp), ke, n4.w, cvp.x, np, sn, nq, c2.x);
+                const float hw = b3(a) * b3(b) * w;
+                Dn += hw;
+                Sc = fmaf(hw, c2.x - cvp.x, Sc);
+                Sv = fmaf(hw * hw, c2.y, Sv);
+            }
+            const float iD = 1.0f / Dn;
+            const float cpr = fmaf(Sc, iD, cvp.x), vpr = Sv * iD * iD;
+            const float A = ab * iD, Bc = bb * iD * iD;
+            const float K2 = 2.0f * Bc * vpr * Dn;
+            float cbar_c = 0.0f, gbar = 0.0f;
+            const float iE2 = iE * iE;
+            // sweep 2: weight adjoints, the centre-role terms and the sigma
+            // partials (the taps' weights recomputed with the same arithmetic)
+#pragma unroll 1
+            for (int b = -2; b <= 2; ++b)
+#pragma unroll
+            for (int a = -2; a <= 2; ++a) {
+                if (a == 0 && b == 0) continue;
+                const int e = c + b * CW + s * a;
+                const float4 nq = s_nz[e];
+                const float2 c2 = s_cv[e];
+                const float w = fused_weight(depth_coef(dzp, a, b, s, sz, eps_zp), ke, n4.w, cvp.x, np, sn, nq, c2.x);
+                const float h = b3(a) * b3(b);
+                const float wbar = h * (A * (c2.x - cpr) - K2) + 2.0f * Bc * h * h * w * c2.y;
+                const float dc = cvp.x - c2.x;
+                const float ww = wbar * w;
+                cbar_c -= ww * sgn(dc) * iE;
+                gbar = fmaf(ww * fabsf(dc), sl * iE2, gbar);
+                s_l = fmaf(ww * fabsf(dc), g * iE2, s_l);
+                const float S = fabsf((float)s * ((float)a * dzp.x + (float)b * dzp.y));
+                const float iF = hw_rcp(fmaf(sz, S, eps_zp));
+                s_z = fmaf(ww * fabsf(n4.w - nq.w), S * iF * iF, s_z);
+                const float xn = fminf(dot3(np, f3(nq)), 1.0f);
+                if (w > 0.0f && xn > 0.0f) s_n = fmaf(ww, hw_log2(xn) * 0.6931471805599453f, s_n);
+            }
+            const float Gb = g > 0.0f ? gbar / (2.0f * g) / sk : 0.0f;
+            D.coef[i] = make_float4(A, Bc, cpr, E);
+            D.aux[i] = make_float4(Gb, cbar_c, K2, 0.0f);
+        }
+    }
+    const double tz = block_sum((double)s_z, red);
+    const double tn = block_sum((double)s_n, red);
+    const double tl = block_sum((double)s_l, red);
+    if (threadIdx.x == 0) {
+        double* o = D.part + ((size_t)D.part_off[LEVEL] + t) * 3;
+        o[0] = tz;
+        o[1] = tn;
+        o[2] = tl;
+    }
+}
+
+// Pass B staging: a centre pixel p's geometry, its coefficients (A, B, c', E)
+// and (c_p, K_p, dz_p).
+struct StagedP {
+    float4 nz, cf, ck;
+};
+
+template <int LEVEL>
+__global__ __launch_bounds__(kSvgfBlock) void adjoint_b_rows(const BwdBatch Bt, const SvgfK P) {
+    constexpr int s = 1 << LEVEL;
+    constexpr int CW = kRowsTX + 4 * s, CH = kRowsTY + 4, GW = kRowsTX + 2;
+    __shared__ float4 s_nz[CH * CW];
+    __shared__ float4 s_cf[CH * CW];
+    __shared__ float4 s_ck[CH * CW];         // (c_p, K_p, dz_p.x, dz_p.y)
+    __shared__ float s_gb[kRowsTY * 3 * GW];  // prefilter adjoint of the rows around each output row
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int j = find_job(Bt.tile0, (int)Bt.n, lb);
+    const BwdDesc& D = Bt.d[j];
+    const int t = (int)(lb - Bt.tile0[j]);
+    const int W = (int)D.W, H = (int)D.H;
+    const int ntx = (W + kRowsTX - 1) / kRowsTX;
+    const int X = t % ntx, rest = t / ntx;
+    const int x0 = X * kRowsTX, y0 = (rest / s) * (kRowsTY * s) + rest % s;
+    const float2* cv = D.save + (size_t)LEVEL * W * H;
+    stage_tile<CH * CW>(
+        [&](int e) {
+            const int px = x0 - 2 * s + e % CW, py = y0 + s * (e / CW - 2);
+            StagedP r{make_float4(0.0f, 0.0f, 0.0f, 0.0f), make_float4(0.0f, 0.0f, 0.0f, 1.0f),
+                      make_float4(0.0f, 0.0f, 0.0f, 0.0f)};
+            if (px >= 0 && px < W && py >= 0 && py < H) {
+                const size_t p = (size_t)py * W + px;
+                r.nz = D.nz[p];
+                r.cf = D.coef[p];
+                const float2 dz = D.dz[p];
+                r.ck = make_float4(cv[p].x, D.aux[p].z, dz.x, dz.y);
+            }
+            return r;
+        },
+        [&](int e, const StagedP& r) {
+            const bool ok = r.nz.w > 0.0f;
+            s_nz[e] = ok ? r.nz : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            s_cf[e] = ok ? r.cf : make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+            s_ck[e] = ok ? r.ck : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        });
+    stage_tile<kRowsTY * 3 * GW>(
+        [&](int e) {
+            const int rx = x0 - 1 + e % GW, ry = y0 + s * (e / (3 * GW)) + (e / GW) % 3 - 1;
+            return (rx >= 0 && rx < W && ry >= 0 && ry < H) ? D.aux[(size_t)ry * W + rx].x : 0.0f;
+        },
+        [&](int e, float v) { s_gb[e] = v; });
+    __syncthreads();
+    const int li = threadIdx.x % kRowsTX, lj = threadIdx.x / kRowsTX;
+    const int x = x0 + li, y = y0 + s * lj;
+    if (x >= W || y >= H) return;
+    const uint32_t L = P.levels;
+    const size_t i = (size_t)y * W + x;
+    float2* out = adj_out(D, LEVEL, L);
+    const int c = (lj + 2) * CW + 2 * s + li;
+    const float4 n4 = s_nz[c];
+    if (!(n4.w > 0.0f)) {
+        out[i] = make_float2(0.0f, 0.0f);
+        return;
+    }
+    const float2 cvq = cv[i];
+    const float sz = P.sz[LEVEL], sn = P.sn[LEVEL];
+    float acc_c = D.aux[i].y, acc_v = 0.0f;
+#pragma unroll
+    for (int b = -2; b <= 2; ++b) {
+#pragma unroll
+        for (int a = -2; a <= 2; ++a) {
+            // centre pixel p = q - s (a, b), whose tap (a, b) is this pixel
+            const int e = c - b * CW - s * a;
+            const float4 cf = s_cf[e];
+            const float h = b3(a) * b3(b);
+            if (a == 0 && b == 0) {
+                acc_c = fmaf(cf.x, h, acc_c);
+                acc_v = fmaf(cf.y, h * h, acc_v);
+                continue;
+            }
+            const float4 np4 = s_nz[e];
+            const float4 ck = s_ck[e];
+            const float cp = ck.x, Kp = ck.y;
+            const float iE = 1.0f / cf.w;
+            const float w = fused_weight(depth_coef(make_float2(ck.z, ck.w), a, b, s, sz, P.eps_z * np4.w),
+                                         kNegLog2e * iE, np4.w, cp, f3(np4), sn, n4, cvq.x);
+            const float wbar = h * (cf.x * (cvq.x - cf.z) - Kp) + 2.0f * cf.y * h * h * w * cvq.y;
+            acc_c += cf.x * h * w + wbar * w * sgn(cp - cvq.x) * iE;
+            acc_v = fmaf(cf.y * h * h, w * w, acc_v);
+        }
+    }
+    // adjoint of the 3x3 prefilter: v_q feeds g of every valid neighbour
+    // (invalid neighbours carry a zero prefilter adjoint)
+#pragma unroll
+    for (int b = -1; b <= 1; ++b)
+#pragma unroll
+        for (int a = -1; a <= 1; ++a) acc_v = fmaf(s_gb[(3 * lj + b + 1) * GW + li + 1 + a], k3(a) * k3(b), acc_v);
+    out[i] = make_float2(acc_c, acc_v);
+}
+
 // grad_sigma[fam * L + l] = sum over frames and tiles, in a fixed order.
 __global__ __launch_bounds__(256) void sigma_reduce_kernel(const BwdBatch Bt, uint32_t L, float* grad_sigma,
                                                            int accumulate) {
@@ -245,8 +507,9 @@ __global__ __launch_bounds__(256) void sigma_reduce_kernel(const BwdBatch Bt, ui
     double acc = 0.0;
     for (uint32_t f = 0; f < Bt.n; ++f) {
         const BwdDesc& D = Bt.d[f];
-        const double* p = D.part + (size_t)l * D.tiles * 3 + fam;
-        for (uint32_t t = threadIdx.x; t < D.tiles; t += 256) acc += p[(size_t)t * 3];
+        const double* p = D.part + (size_t)D.part_off[l] * 3 + fam;
+        const uint32_t nt = D.part_off[l + 1] - D.part_off[l];
+        for (uint32_t t = threadIdx.x; t < nt; t += 256) acc += p[(size_t)t * 3];
     }
 #pragma unroll
     for (int k = 32; k > 0; k >>= 1) acc += __shfl_xor(acc, k, 64);
@@ -255,6 +518,31 @@ __global__ __launch_bounds__(256) void sigma_reduce_kernel(const BwdBatch Bt, ui
     if (threadIdx.x == 0) {
         const double tot = red[0] + red[1] + red[2] + red[3];
         grad_sigma[o] = accumulate ? (float)((double)grad_sigma[o] + tot) : (float)tot;
+    }
+}
+
+void launch_adjoint_rows(uint32_t level, dim3 grid, hipStream_t s, const BwdBatch& B, const SvgfK& K) {
+    switch (level) {
+        case 0:
+            hipLaunchKernelGGL(adjoint_a_rows<0>, grid, dim3(kSvgfBlock), 0, s, B, K);
+            hipLaunchKernelGGL(adjoint_b_rows<0>, grid, dim3(kSvgfBlock), 0, s, B, K);
+            break;
+        case 1:
+            hipLaunchKernelGGL(adjoint_a_rows<1>, grid, dim3(kSvgfBlock), 0, s, B, K);
+            hipLaunchKernelGGL(adjoint_b_rows<1>, grid, dim3(kSvgfBlock), 0, s, B, K);
+            break;
+        case 2:
+            hipLaunchKernelGGL(adjoint_a_rows<2>, grid, dim3(kSvgfBlock), 0, s, B, K);
+            hipLaunchKernelGGL(adjoint_b_rows<2>, grid, dim3(kSvgfBlock), 0, s, B, K);
+            break;
+        case 3:
+            hipLaunchKernelGGL(adjoint_a_rows<3>, grid, dim3(kSvgfBlock), 0, s, B, K);
+            hipLaunchKernelGGL(adjoint_b_rows<3>, grid, dim3(kSvgfBlock), 0, s, B, K);
+            break;
+        default:
+            hipLaunchKernelGGL(adjoint_a_rows<4>, grid, dim3(kSvgfBlock), 0, s, B, K);
+            hipLaunchKernelGGL(adjoint_b_rows<4>, grid, dim3(kSvgfBlock), 0, s, B, K);
+            break;
     }
 }
 
@@ -299,6 +587,11 @@ dhr_status dhr_svgf_backward(dhr_ctx* ctx, const dhr_svgf_params* params, const 
         d.g1 = reinterpret_cast<float2*>(w + HW * 24);
         d.aux = reinterpret_cast<float4*>(w + HW * 32);
         d.part = reinterpret_cast<double*>(w + HW * 48);
+        uint32_t acc = 0;
+        for (uint32_t l = 0; l <= DHR_MAX_LEVELS; ++l) {
+            d.part_off[l] = acc;
+            if (l < L) acc += adjoint_tiles(F.W, F.H, l);
+        }
     }
     DeviceGuard g(ctx->device);
     const SvgfK K = [&] {
@@ -325,16 +618,22 @@ dhr_status dhr_svgf_backward(dhr_ctx* ctx, const dhr_svgf_params* params, const 
         std::memset(&B, 0, sizeof B);
         const size_t n = std::min<size_t>(kBwdMaxB, descs.size() - b0);
         B.n = (uint32_t)n;
-        uint64_t acc = 0;
-        for (size_t k = 0; k < n; ++k) {
-            B.tile0[k] = (uint32_t)acc;
-            B.d[k] = descs[b0 + k];
-            acc += descs[b0 + k].tiles;
-        }
-        B.tile0[n] = (uint32_t)acc;
+        for (size_t k = 0; k < n; ++k) B.d[k] = descs[b0 + k];
         for (int l = (int)L - 1; l >= 0; --l) {
-            hipLaunchKernelGGL(adjoint_a_kernel, dim3((uint32_t)acc), dim3(kSvgfBlock), 0, s, B, K, (uint32_t)l);
-            hipLaunchKernelGGL(adjoint_b_kernel, dim3((uint32_t)acc), dim3(kSvgfBlock), 0, s, B, K, (uint32_t)l);
+            // workgroup prefix of this level's tiling
+            uint64_t tot = 0;
+            for (size_t k = 0; k < n; ++k) {
+                B.tile0[k] = (uint32_t)tot;
+                tot += adjoint_tiles(descs[b0 + k].W, descs[b0 + k].H, (uint32_t)l);
+            }
+            B.tile0[n] = (uint32_t)tot;
+            if (tot > 0x7FFFFFFFull) return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_backward: batch too large");
+            if (l <= (int)kAdjRowsMax) {
+                launch_adjoint_rows((uint32_t)l, dim3((uint32_t)tot), s, B, K);
+            } else {
+                hipLaunchKernelGGL(adjoint_a_direct, dim3((uint32_t)tot), dim3(kSvgfBlock), 0, s, B, K, (uint32_t)l);
+                hipLaunchKernelGGL(adjoint_b_direct, dim3((uint32_t)tot), dim3(kSvgfBlock), 0, s, B, K, (uint32_t)l);
+            }
         }
         hipLaunchKernelGGL(sigma_reduce_kernel, dim3(3 * L), dim3(256), 0, s, B, L, grad_sigma, b0 > 0 ? 1 : 0);
         st = check_launch(ctx, "dhr_svgf_backward");

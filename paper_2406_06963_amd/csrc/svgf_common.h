@@ -84,6 +84,25 @@ __device__ __forceinline__ void stage_tile(Load load, Store store) {
     }
 }
 
+// Row-class tiles of the a-trous levels at stride s = 2^level: a workgroup
+// owns 64 consecutive pixels of 4 rows that are s apart (rows congruent mod
+// s); tile t of a frame is column block t % tx, then row class, then block
+// of 4s rows.
+constexpr int kRowsTX = 64, kRowsTY = kSvgfBlock / kRowsTX;
+
+__host__ __device__ constexpr uint32_t rows_tiles(uint32_t W, uint32_t H, int level) {
+    return ((W + kRowsTX - 1) / kRowsTX) * (1u << level) * ((H + (kRowsTY << level) - 1) / (kRowsTY << level));
+}
+
+// The adjoint runs levels up to kAdjRowsMax on row-class tiles, deeper levels
+// (whose staged neighbourhood would not fit in LDS) on 16 x 16 tiles.
+constexpr uint32_t kAdjRowsMax = 4;
+
+__host__ __device__ constexpr uint32_t adjoint_tiles(uint32_t W, uint32_t H, uint32_t level) {
+    return level <= kAdjRowsMax ? rows_tiles(W, H, (int)level)
+                                : ((W + kSvgfTile - 1) / kSvgfTile) * ((H + kSvgfTile - 1) / kSvgfTile);
+}
+
 // Geometry and (c, var) of one staged pixel
 struct Staged {
     float4 nz;
