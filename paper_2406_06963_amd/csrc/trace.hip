@@ -1,9 +1,10 @@
 // Ray kernels: the G-buffer of primary rays and the stochastic visibility
 // rays (ambient occlusion, Section 3.2; soft shadows, Section 3.1).
 //
-// Layout: one lane per pixel; a 128-lane workgroup covers a 16 x 8 tile and
-// each 64-lane wave an 8 x 8 square, whose rays traverse the tree together
-// (one walk per wave, the stack one LDS column per wave).  Jobs of a ragged
+// Layout: a 128-lane workgroup covers a 16 x 8 pixel tile; a wave's 64 rays
+// traverse the tree together (one walk per wave, the stack one LDS column per
+// wave): one ray of each pixel of an 8 x 8 square, or, for a stream with an
+// even ray count, P rays of each pixel of an 8 x 8/P block.  Jobs of a ragged
 // batch are passed by value in the kernel arguments.
 #include <cmath>
 #include <cstring>
@@ -73,87 +74,147 @@ __device__ __forceinline__ float3 cam_dir(const CamD& c, float px, float py, uin
     return normalize3(d);
 }
 
+// Ray `sample` of stream st (0 = AO, l + 1 = light l) of pixel (x, y) with
+// offset origin o and normal n.  `decided` rays need no tracing: invalid
+// pixels, points inside a sphere light (unoccluded), light behind the
+// surface (occluded); `occ` then holds the answer.
+__device__ __forceinline__ void make_ray(const TraceDesc& D, uint32_t st, uint32_t sample, uint32_t x, uint32_t y,
+                                         float3 o, float3 n, bool valid, Ray& r, bool& decided, bool& occ) {
+    occ = true;
+    decided = !valid;
+    r.o = o;
+    r.d = n;
+    r.tmax = 0.0f;
+    if (!valid) return;
+    const float2 u = ray_uniforms(D.seed, D.client, x, y, D.frame, st, st == 0 ? D.ao_off + sample : sample);
+    if (st == 0) {
+        r.d = sample_cosine(n, u.x, u.y);
+        r.tmax = D.ao_r;
+        return;
+    }
+    const LightD& L = D.lights[st - 1];
+    if (L.kind == 0) {
+        r.d = sample_cone(f3(L.v[0], L.v[1], L.v[2]), L.k, u.x, u.y);
+        r.tmax = __builtin_inff();
+    } else {
+        const float3 Dv = f3(L.v[0], L.v[1], L.v[2]) - o;
+        const float dist = sqrtf(dot3(Dv, Dv));
+        if (dist <= L.radius) {
+            decided = true;
+            occ = false;
+            return;
+        }
+        const float3 axis = Dv * (1.0f / dist);
+        const float rr = L.radius / dist;
+        const float q = rr * rr;
+        const float k = q / (1.0f + sqrtf(1.0f - q));
+        r.d = sample_cone(axis, k, u.x, u.y);
+        const float b = dot3(r.d, Dv);
+        const float c = dist * dist - L.radius * L.radius;
+        r.tmax = b - sqrtf(fmaxf(b * b - c, 0.0f));
+    }
+    if (dot3(n, r.d) <= 0.0f) {
+        decided = true;
+        occ = true;
+    }
+}
+
+// Rays of one pixel a stream traces side by side in one wave: the largest
+// power of two up to 8 that divides the stream's ray count.  A wave then
+// covers 64 / P pixels (an 8 x 8/P block) with P rays each, whose paths
+// through the tree overlap more than those of 64 pixels one ray apart.
+__device__ __forceinline__ uint32_t pack_of(uint32_t nr) {
+    return (nr % 8 == 0) ? 8 : (nr % 4 == 0) ? 4 : (nr % 2 == 0) ? 2 : 1;
+}
+
 // COUNT: the instrumented variant that also tallies rays, node visits, leaf
 // visits and triangle tests into `counters` (device uint64[4]).
 template <bool COUNT>
 __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsigned long long* counters) {
     __shared__ int stack[kStack * (kBlock / 64)];
+    __shared__ float4 s_o[kBlock];   // the tile's ray origins, w = 1 for a valid pixel
+    __shared__ float4 s_n[kBlock];   // and normals
+    __shared__ uint32_t s_cnt[kBlock];
+    __shared__ unsigned long long s_bits[kBlock];
     const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
     const TraceDesc& D = B.d[j];
+    const uint32_t t = blockIdx.x - B.tile0[j];
+    const uint32_t tx0 = (t % D.tiles_x) * kTileW, ty0 = (t / D.tiles_x) * kTileH;
     uint32_t x, y;
-    tile_pixel(blockIdx.x - B.tile0[j], D.tiles_x, x, y);
-    if (x >= D.W || y >= D.H) return;
+    tile_pixel(t, D.tiles_x, x, y);
+    const bool inside = x < D.W && y < D.H;
     const size_t HW = (size_t)D.W * D.H;
-    const size_t i = (size_t)y * D.W + x;
+    const size_t i = inside ? (size_t)y * D.W + x : 0;
     const float4 p4 = D.pos[i];
     const float4 n4 = D.nz[i];
-    const bool valid = n4.w > 0.0f;
+    const bool valid = inside && n4.w > 0.0f;
     const float3 n = f3(n4);
     const float3 p = f3(p4);
     float eps = D.eps_abs;
     if (!(eps > 0.0f)) eps = fmaxf(1e-3f * D.ao_r, fmaxf(fmaxf(fabsf(p.x), fabsf(p.y)), fabsf(p.z)) * 0x1p-17f);
     const float3 o = p + n * eps;
+    s_o[threadIdx.x] = make_float4(o.x, o.y, o.z, valid ? 1.0f : 0.0f);
+    s_n[threadIdx.x] = make_float4(n.x, n.y, n.z, 0.0f);
+    __syncthreads();
     TravCount tc;
     uint32_t n_rays = 0;
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int* wstk = stack + w * kStack;
 
-    int* wstk = stack + (threadIdx.x >> 6) * kStack;
     for (uint32_t st = 0; st <= D.n_lights; ++st) {
         const uint32_t nr = st == 0 ? D.n_ao : D.n_shadow;
+        const uint32_t P = pack_of(nr);
         uint32_t cnt = 0;
         uint64_t bits = 0;
-        for (uint32_t s = 0; s < nr; ++s) {
-            bool occ = true;   // invalid pixels count every ray as unoccluded below
-            bool decided = !valid;
-            Ray r;
-            r.o = o;
-            r.d = n;
-            r.tmax = 0.0f;
-            if (valid) {
-                const float2 u = ray_uniforms(D.seed, D.client, x, y, D.frame, st, st == 0 ? D.ao_off + s : s);
-                if (st == 0) {
-                    r.d = sample_cosine(n, u.x, u.y);
-                    r.tmax = D.ao_r;
-                } else {
-                    const LightD& L = D.lights[st - 1];
-                    if (L.kind == 0) {
-                        r.d = sample_cone(f3(L.v[0], L.v[1], L.v[2]), L.k, u.x, u.y);
-                        r.tmax = __builtin_inff();
-                    } else {
-                        const float3 Dv = f3(L.v[0], L.v[1], L.v[2]) - o;
-                        const float dist = sqrtf(dot3(Dv, Dv));
-                        if (dist <= L.radius) {
-                            decided = true;
-                            occ = false;
-                        } else {
-                            const float3 axis = Dv * (1.0f / dist);
-                            const float rr = L.radius / dist;
-                            const float q = rr * rr;
-                            const float k = q / (1.0f + sqrtf(1.0f - q));
-                            r.d = sample_cone(axis, k, u.x, u.y);
-                            const float b = dot3(r.d, Dv);
-                            const float c = dist * dist - L.radius * L.radius;
-                            r.tmax = b - sqrtf(fmaxf(b * b - c, 0.0f));
-                        }
-                    }
-                    if (!decided && dot3(n, r.d) <= 0.0f) {
-                        decided = true;
-                        occ = true;
-                    }
-                }
+        if (P > 1) {
+            s_cnt[threadIdx.x] = 0;
+            s_bits[threadIdx.x] = 0;
+            __syncthreads();
+        }
+        for (uint32_t it = 0; it < nr; ++it) {
+            // P == 1: ray `it` of the lane's own pixel.  P > 1: step it of the
+            // stream covers block b = 2 (it % P) + w of the 16 x 8 tile (8 x 8/P
+            // pixels), P rays of each pixel, counted in LDS.
+            uint32_t src = threadIdx.x, s = it, px = x, py = y;
+            if (P > 1) {
+                const uint32_t b = 2 * (it % P) + w, q = lane / P;
+                const uint32_t lx = (b & 1) * 8 + q % 8, ly = (b >> 1) * (8 / P) + q / 8;
+                src = (lx / 8) * 64 + ly * 8 + lx % 8;
+                s = (it / P) * P + lane % P;
+                px = tx0 + lx;
+                py = ty0 + ly;
             }
+            const float4 so = s_o[src], sn = s_n[src];
+            const bool v = so.w > 0.0f;
+            Ray r;
+            bool decided, occ;
+            make_ray(D, st, s, px, py, f3(so), f3(sn), v, r, decided, occ);
             const bool h = any_hit<COUNT>(D.nodes, D.tris, r, !decided, wstk, &tc);
             if (!decided) occ = h;
             if (COUNT && !decided) ++n_rays;
-            if (!valid || !occ) {
-                ++cnt;
-                if (s < 64) bits |= 1ull << s;
+            if (!v || !occ) {
+                if (P == 1) {
+                    ++cnt;
+                    if (s < 64) bits |= 1ull << s;
+                } else {
+                    atomicAdd(&s_cnt[src], 1u);
+                    if (s < 64) atomicOr(&s_bits[src], 1ull << s);
+                }
             }
         }
-        if (st == 0)
-            D.ao[i] = (uint8_t)cnt;
-        else
-            D.sh[(size_t)(st - 1) * HW + i] = (uint8_t)cnt;
-        if (D.bits) D.bits[(size_t)st * HW + i] = bits;
+        if (P > 1) {
+            __syncthreads();
+            cnt = s_cnt[threadIdx.x];
+            bits = s_bits[threadIdx.x];
+        }
+        if (inside) {
+            if (st == 0)
+                D.ao[i] = (uint8_t)cnt;
+            else
+                D.sh[(size_t)(st - 1) * HW + i] = (uint8_t)cnt;
+            if (D.bits) D.bits[(size_t)st * HW + i] = bits;
+        }
+        __syncthreads();  // s_cnt / s_bits are reused by the next stream
     }
     if (COUNT) {
         // one vector atomic per lane (instrumented runs only)
