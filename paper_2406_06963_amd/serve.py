@@ -96,7 +96,7 @@ def resident_bytes(W: int, H: int, n_lights: int = 1) -> int:
 
 
 class Server:
-    def __init__(self, executor, budget_bytes: float = 200e9, max_batch: int = 16, max_inflight: int = 3,
+    def __init__(self, executor, budget_bytes: float = 200e9, max_batch: int = 8, max_inflight: int = 3,
                  max_stale_s: float = 0.25, idle_evict_s: float = 2.0, clock=time.perf_counter,
                  keep_outputs: bool = False):
         self.ex = executor

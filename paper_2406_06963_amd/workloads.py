@@ -424,6 +424,9 @@ PRESETS = {
     "room720": Preset("room720", "room", "walk", 1280, 720, 60, 1, 0.5, 1, seed=2),
     # 1920x1080 terrain, 120 frames, 1 AO (r=1) + 2 shadow rays
     "terrain1080": Preset("terrain1080", "terrain", "flyover", 1920, 1080, 120, 1, 1.0, 2, seed=3),
+    # ragged sizes for edge cases: no side a multiple of any kernel tile
+    "ragged": Preset("ragged", "room", "walk", 141, 77, 4, 3, 0.5, 2, seed=4),
+    "sliver": Preset("sliver", "spheres", "orbit", 5, 131, 3, 1, 1.0, 4, seed=5),
 }
 
 
