@@ -1,8 +1,10 @@
 // Modified SVGF forward (Section 3.3): temporal accumulation, variance
 // estimate and the iterated a-trous levels.  One lane per pixel, 16 x 16
 // pixel workgroups; every pass covers a ragged batch of frames in one launch.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <vector>
 
 #include "svgf_common.h"
@@ -545,7 +547,10 @@ SvgfK kparams(const dhr_svgf_params* p) {
     k.alpha_m = p->alpha_moments;
     for (int l = 0; l < DHR_MAX_LEVELS; ++l) {
         k.sz[l] = p->sigma_z[l];
-        k.sn[l] = p->sigma_n[l];
+        // sigma_n = 0 (weight 1 for every n_p . n_q > 0) as the smallest
+        // normal float: same weights, and the tap loop's exponent stays -inf
+        // (weight 0) where n_p . n_q = 0
+        k.sn[l] = std::max(p->sigma_n[l], std::numeric_limits<float>::min());
         k.sl[l] = p->sigma_l[l];
     }
     k.eps_z = p->eps_z_rel;

@@ -148,13 +148,17 @@ __device__ __forceinline__ float fused_weight(float kz, float ke, float zp, floa
 
 // One tap of a level whose staged neighbourhood holds a zero normal for
 // invalid pixels (so n_p . n_q = 0 and the weight vanishes): accumulates the
-// weight sum, the weighted deviation and the squared-weight variance.
+// weight sum, the weighted deviation and the squared-weight variance.  The
+// normal term clamps n_p . n_q to [0, 1]; at 0 its log2 is -inf, the exponent
+// -inf and the weight exactly 0 with no test, provided sn > 0 (the parameter
+// block raises sigma_n = 0 to the smallest normal float, whose weight x^sn
+// rounds to 1 for every x > 0).
 __device__ __forceinline__ void accumulate_tap(float h, float kz, float ke, float zp, float cp, float3 np, float sn,
                                                float4 nq, float2 cvq, float& Dn, float& Sc, float& Sv) {
-    const float x = fminf(dot3(np, f3(nq)), 1.0f);
+    const float x = __builtin_amdgcn_fmed3f(dot3(np, f3(nq)), 0.0f, 1.0f);
     const float d = cvq.x - cp;
     const float e = fmaf(kz, fabsf(zp - nq.w), fmaf(ke, fabsf(d), sn * hw_log2(x)));
-    const float hw = x > 0.0f ? h * hw_exp2(e) : 0.0f;
+    const float hw = h * hw_exp2(e);
     Dn += hw;
     Sc = fmaf(hw, d, Sc);
     Sv = fmaf(hw * hw, cvq.y, Sv);
