@@ -72,7 +72,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--preset", default="terrain1080")
-    ap.add_argument("--cpu-frames", type=int, default=2, help="frames of the oracle CPU baseline (0 = skip)")
+    ap.add_argument("--cpu-frames", type=int, default=16,
+                    help="frames of the oracle CPU baseline, about 10-30 s of host work (0 = skip)")
     ap.add_argument("--no-counters", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="serving run per mode (0 = skip)")
     ap.add_argument("--serve-clients", type=int, default=64)
@@ -117,7 +118,7 @@ def main():
     pr = wl.preset(args.preset)
     W, H = pr.W, pr.H
     HW = W * H
-    nfr = args.warmup + args.steps + 1
+    nfr = args.warmup + max(args.steps, args.cpu_frames) + 1
     scene = wl.make_scene(pr.scene)
     cams = wl.camera_path(pr.camera, nfr, scene)
     lights = wl.lights_for(pr.scene)

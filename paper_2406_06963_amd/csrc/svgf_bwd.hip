@@ -498,25 +498,37 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_b_rows(const BwdBatch Bt, 
     out[i] = make_float2(acc_c, acc_v);
 }
 
-// grad_sigma[fam * L + l] = sum over frames and tiles, in a fixed order.
-__global__ __launch_bounds__(256) void sigma_reduce_kernel(const BwdBatch Bt, uint32_t L, float* grad_sigma,
-                                                           int accumulate) {
-    __shared__ double red[4];
+// grad_sigma[fam * L + l] = sum over frames and workgroup partials, in a
+// fixed order: lane t of the block keeps four independent sums (partials t,
+// t + 1024, t + 2048, t + 3072 of each stride of 4096) so that four loads are
+// in flight per lane.
+constexpr int kReduceBlock = 1024;
+
+__global__ __launch_bounds__(kReduceBlock) void sigma_reduce_kernel(const BwdBatch Bt, uint32_t L, float* grad_sigma,
+                                                                    int accumulate) {
+    __shared__ double red[kReduceBlock / 64];
     const uint32_t o = blockIdx.x;  // fam * L + l
     const uint32_t fam = o / L, l = o % L;
-    double acc = 0.0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     for (uint32_t f = 0; f < Bt.n; ++f) {
         const BwdDesc& D = Bt.d[f];
         const double* p = D.part + (size_t)D.part_off[l] * 3 + fam;
         const uint32_t nt = D.part_off[l + 1] - D.part_off[l];
-        for (uint32_t t = threadIdx.x; t < nt; t += 256) acc += p[(size_t)t * 3];
+        for (uint32_t t = threadIdx.x; t < nt; t += 4 * kReduceBlock) {
+            a0 += p[(size_t)t * 3];
+            if (t + kReduceBlock < nt) a1 += p[(size_t)(t + kReduceBlock) * 3];
+            if (t + 2 * kReduceBlock < nt) a2 += p[(size_t)(t + 2 * kReduceBlock) * 3];
+            if (t + 3 * kReduceBlock < nt) a3 += p[(size_t)(t + 3 * kReduceBlock) * 3];
+        }
     }
+    double acc = (a0 + a1) + (a2 + a3);
 #pragma unroll
     for (int k = 32; k > 0; k >>= 1) acc += __shfl_xor(acc, k, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const double tot = red[0] + red[1] + red[2] + red[3];
+        double tot = 0.0;
+        for (int k = 0; k < kReduceBlock / 64; ++k) tot += red[k];
         grad_sigma[o] = accumulate ? (float)((double)grad_sigma[o] + tot) : (float)tot;
     }
 }
@@ -635,7 +647,7 @@ dhr_status dhr_svgf_backward(dhr_ctx* ctx, const dhr_svgf_params* params, const 
                 hipLaunchKernelGGL(adjoint_b_direct, dim3((uint32_t)tot), dim3(kSvgfBlock), 0, s, B, K, (uint32_t)l);
             }
         }
-        hipLaunchKernelGGL(sigma_reduce_kernel, dim3(3 * L), dim3(256), 0, s, B, L, grad_sigma, b0 > 0 ? 1 : 0);
+        hipLaunchKernelGGL(sigma_reduce_kernel, dim3(3 * L), dim3(kReduceBlock), 0, s, B, L, grad_sigma, b0 > 0 ? 1 : 0);
         st = check_launch(ctx, "dhr_svgf_backward");
         if (st != DHR_OK) return st;
     }
