@@ -270,7 +270,8 @@ typedef struct {
     float* hist_out;            /* device float[HW][4]; must not alias hist_in */
     float* out;                 /* device float[HW]: filtered AO */
     float* save;                /* NULL or device float[levels][HW][2]: the input
-                                   (c, var) of every level, for dhr_svgf_backward */
+                                   (c, var) of every level, for dhr_svgf_backward
+                                   (levels >= 1 hold var = -3e38 on invalid pixels) */
     float* work;                /* device scratch of dhr_svgf_workspace_bytes(W,H,p,0)
                                    bytes (16-byte aligned) */
     float pix;                  /* 2 tan(fov_y / 2) / H of the current camera */
