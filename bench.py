@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="serving run per mode (0 = skip)")
     ap.add_argument("--serve-clients", type=int, default=64)
     ap.add_argument("--bwd-frames", type=int, default=16, help="frames of the differentiation run (0 = skip)")
+    ap.add_argument("--other-steps", type=int, default=20,
+                    help="timed steps of the 64x64 and 720p workloads (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB three times (a plain copy kernel of "
                          "known size, to calibrate hardware byte counters; 0 = skip)")
@@ -236,6 +238,23 @@ def main():
         "roofline_trace": roof_trace,
     }
 
+    # wire form of the last frame: AO bytes + per-light bits (memory-bound)
+    q8 = torch.empty(HW, dtype=torch.uint8, device=dev)
+    m8 = torch.empty(HW, dtype=torch.uint8, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    B.dhr_encode_frame(ctx, value=out, q=q8, shadow_count=sh, n_shadow=pr.n_shadow, mask=m8)
+    e0.record()
+    for _ in range(200):
+        B.dhr_encode_frame(ctx, value=out, q=q8, shadow_count=sh, n_shadow=pr.n_shadow, mask=m8)
+    e1.record()
+    torch.cuda.synchronize()
+    enc_s = e0.elapsed_time(e1) / 200 / 1e3
+    enc_bytes = HW * (4 + len(lights) + 2)
+    line["encode"] = {"us": enc_s * 1e6, "bytes_per_px": 4 + len(lights) + 2,
+                      "roofline": {"bound": "hbm", "achieved": enc_bytes / enc_s / 1e9, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": enc_bytes / enc_s / 1e9 / HBM_PEAK_GBS}}
+    if args.other_steps > 0:
+        line["other_workloads"] = {name: bench_preset(B, ctx, name, args.other_steps) for name in ("tiny", "room720")}
     if args.bwd_frames > 0:
         line["differentiation"] = bench_backward(B, ctx, args.bwd_frames)
     if args.serve_seconds > 0:
@@ -244,6 +263,58 @@ def main():
     if args.cpu_frames > 0:
         line["cpu_baseline"] = cpu_baseline(pr, scene, cams, lights, args)
     print(json.dumps(line), flush=True)
+
+
+def bench_preset(B, ctx, name, steps, warmup=5):
+    """The same step (G-buffer, rays, SVGF with resident history) on another
+    workload: per-pass device time from HIP events, rates of the ray and
+    filter passes."""
+    import torch
+
+    from paper_2406_06963_amd import workloads as wl
+    pr = wl.preset(name)
+    W, H, HW = pr.W, pr.H, pr.W * pr.H
+    scene = wl.make_scene(pr.scene)
+    cams = wl.camera_path(pr.camera, warmup + steps, scene)
+    lights = wl.lights_for(pr.scene)
+    bvh = B.dhr_build_bvh(ctx, scene.tris, scene.obj_id)
+    P = B.svgf_params(levels=pr.levels, alpha=pr.alpha)
+    gb = [B.gbuffer_tensors(W, H) for _ in range(2)]
+    hist = [torch.empty(HW, 4, device="cuda") for _ in range(2)]
+    ao = torch.empty(HW, dtype=torch.uint8, device="cuda")
+    sh = torch.empty(max(len(lights), 1), HW, dtype=torch.uint8, device="cuda")
+    out = torch.empty(HW, device="cuda")
+    work = torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device="cuda")
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    valid = 0
+    for f in range(warmup + steps):
+        cur, prv = gb[f % 2], gb[(f + 1) % 2]
+        e = ev[f - warmup] if f >= warmup else None
+        if e:
+            e[0].record()
+        B.dhr_gbuffer(ctx, bvh, cams[f], cams[f - 1] if f else None, W, H, cur["pos"], cur["nz"], cur["dz"], cur["mv"])
+        if e:
+            e[1].record()
+        B.dhr_trace_visibility(ctx, bvh, B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao,
+                                                        ao_radius=pr.ao_radius, n_shadow=pr.n_shadow, lights=lights),
+                               cur["pos"], cur["nz"], ao, sh)
+        if e:
+            e[2].record()
+        fr = B.svgf_frame(W, H, pr.n_ao, ao, cur["pos"], cur["nz"], cur["dz"], cur["mv"],
+                          prv["pos"] if f else None, prv["nz"] if f else None, hist[(f + 1) % 2] if f else None,
+                          hist[f % 2], out, B.pix_angle(cams[f], H), work=work)
+        B.dhr_svgf_filter(ctx, P, [fr])
+        if e:
+            e[3].record()
+            valid += int((cur["nz"][:, 3] > 0).sum().item())
+    torch.cuda.synchronize()
+    t = [sum(x[k].elapsed_time(x[k + 1]) for x in ev) / steps for k in range(3)]
+    rays = valid / steps * (pr.n_ao + len(lights) * pr.n_shadow)
+    return {"workload": f"{name}: {W}x{H}, {pr.scene} scene ({scene.n_tris} tris), {pr.n_ao} AO + {pr.n_shadow} "
+                        f"shadow rays/px, {pr.levels}-level SVGF", "steps": steps,
+            "pass_ms": {"gbuf": t[0], "trace": t[1], "svgf": t[2]},
+            "trace_mrays_s": rays / (t[1] / 1e3) / 1e6, "svgf_mpix_s": HW / (t[2] / 1e3) / 1e6,
+            "step_mrays_s": rays / (sum(t) / 1e3) / 1e6}
 
 
 def bench_backward(B, ctx, n_frames):

@@ -329,6 +329,22 @@ uint64_t dhr_svgf_workspace_bytes(uint32_t W, uint32_t H, const dhr_svgf_params*
 dhr_status dhr_set_trace_counters(dhr_ctx* ctx, uint64_t* counters);
 
 /* ------------------------------------------------------------------------
+ * Wire form of a served frame (Section 3.2: the AO a client receives is one
+ * byte per pixel; Section 3.1, Fig. 1: one visibility bit per light).
+ *   value  device float[n] (e.g. the filtered AO) or NULL -> q device
+ *          uint8[n]: q = floor(255 * clamp(x, 0, 1) + 1/2), evaluated in fp32
+ *          without fused multiply-add; NaN gives 0
+ *   shadow_count device uint8[n_lights][n] (the trace output) or NULL ->
+ *          mask device uint8[n]: bit l set iff 2 * count_l >= n_shadow (light
+ *          l reached by at least half of its rays; with one ray per light,
+ *          that ray), light 0 = least significant bit
+ * Errors: INVALID_ARG (an input without its output, n_lights outside 1..8 or
+ * n_shadow == 0 with shadow_count, n > 2^36).
+ * ------------------------------------------------------------------------ */
+dhr_status dhr_encode_frame(dhr_ctx* ctx, const float* value, uint8_t* q, const uint8_t* shadow_count,
+                            uint32_t n_lights, uint32_t n_shadow, uint8_t* mask, uint64_t n, dhr_stream stream);
+
+/* ------------------------------------------------------------------------
  * The random-number generator alone (ray generation uses it in-kernel):
  * n counters (device uint32[n][4]) under key (k0, k1) -> device
  * uint32[n][4].

@@ -95,6 +95,8 @@ def _declare(L):
     L.orc_svgf_spatial.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
     L.orc_svgf_spatial_vjp.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
     L.orc_svgf_spatial_jvp.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
+    L.orc_quantize_u8.argtypes = [vp, vp, i64]
+    L.orc_light_mask.argtypes = [vp, i32, i32, i64, vp]
     L.orc_num_threads.restype = i32
     L.orc_set_num_threads.argtypes = [i32]
 
@@ -331,3 +333,19 @@ def id_bits(pos) -> np.ndarray:
     """Object ids stored in pos.w."""
     return np.ascontiguousarray(pos[:, 3]).view(np.uint32)
 
+
+def quantize_u8(x) -> np.ndarray:
+    """One byte per value: floor(255 clamp(x, 0, 1) + 1/2) in fp32 (NaN -> 0)."""
+    x = np.ascontiguousarray(x, dtype=np.float32).ravel()
+    q = np.empty(x.size, np.uint8)
+    lib().orc_quantize_u8(_p(x), _p(q), x.size)
+    return q
+
+
+def light_mask(shadow_count, n_shadow: int) -> np.ndarray:
+    """Bit l set where at least half of light l's n_shadow rays reach it."""
+    sc = np.ascontiguousarray(shadow_count, dtype=np.uint8)
+    L, hw = sc.shape
+    m = np.empty(hw, np.uint8)
+    lib().orc_light_mask(_p(sc), L, n_shadow, hw, _p(m))
+    return m

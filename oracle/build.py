@@ -11,7 +11,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["orc_rng.cpp", "orc_geom.cpp", "orc_render.cpp", "orc_svgf.cpp", "orc_svgf_adjoint.cpp"]
+SOURCES = ["orc_rng.cpp", "orc_geom.cpp", "orc_render.cpp", "orc_svgf.cpp", "orc_svgf_adjoint.cpp", "orc_encode.cpp"]
 LIB = os.path.join(HERE, "liborc.so")
 
 

@@ -128,6 +128,12 @@ void orc_svgf_spatial_jvp(const orc_svgf_params*, int W, int H, const double* cv
                           const float* nz, const float* dz, const double* dcv,
                           const double* dsigma, double* dout);
 
+/* ---- wire form of a served frame ---- */
+/* q = floor(255 * clamp(x, 0, 1) + 1/2) in fp32; NaN and negatives give 0 */
+void orc_quantize_u8(const float* x, uint8_t* q, int64_t n);
+/* bit l of mask[i] = 2 * shadow_count[l][i] >= n_shadow (light l visible) */
+void orc_light_mask(const uint8_t* shadow_count, int n_lights, int n_shadow, int64_t hw, uint8_t* mask);
+
 int orc_num_threads(void);
 void orc_set_num_threads(int n);
 

@@ -104,7 +104,8 @@ class dhr_svgf_bwd_frame(C.Structure):
 EXPORTS = ["dhr_create", "dhr_destroy", "dhr_last_error", "dhr_sync", "dhr_version", "dhr_build_bvh",
            "dhr_bvh_get_info", "dhr_bvh_destroy", "dhr_gbuffer", "dhr_trace_visibility", "dhr_gbuffer_batch",
            "dhr_trace_visibility_batch", "dhr_svgf_default_params", "dhr_svgf_filter", "dhr_svgf_spatial_forward",
-           "dhr_svgf_backward", "dhr_svgf_workspace_bytes", "dhr_philox4x32_10", "dhr_set_trace_counters"]
+           "dhr_svgf_backward", "dhr_svgf_workspace_bytes", "dhr_philox4x32_10", "dhr_set_trace_counters",
+           "dhr_encode_frame"]
 
 _lib = None
 
@@ -145,6 +146,7 @@ def load(path: str = LIB_PATH):
     L.dhr_svgf_workspace_bytes.restype = u64
     L.dhr_philox4x32_10.argtypes = [vp, u32, u32, vp, vp, u64, vp]
     L.dhr_set_trace_counters.argtypes = [vp, vp]
+    L.dhr_encode_frame.argtypes = [vp, vp, vp, vp, u32, u32, vp, u64, vp]
     _lib = L
     return L
 
@@ -396,6 +398,14 @@ def dhr_philox4x32_10(ctx, key, ctr, out, stream=None):
     n = ctr.numel() // 4
     _check(ctx, load().dhr_philox4x32_10(ctx.handle, int(key[0]), int(key[1]), _ptr(ctr), _ptr(out), n,
                                          _stream(stream)), "dhr_philox4x32_10")
+
+
+def dhr_encode_frame(ctx, value=None, q=None, shadow_count=None, n_shadow=1, mask=None, stream=None):
+    """value: float tensor [n] -> q uint8 [n]; shadow_count uint8 [L, n] -> mask uint8 [n]."""
+    n = value.numel() if value is not None else shadow_count.shape[1]
+    L = shadow_count.shape[0] if shadow_count is not None else 0
+    _check(ctx, load().dhr_encode_frame(ctx.handle, _ptr(value), _ptr(q), _ptr(shadow_count), L, n_shadow, _ptr(mask),
+                                        n, _stream(stream)), "dhr_encode_frame")
 
 
 # ----------------------------------------------------------------------------
