@@ -238,6 +238,37 @@ def main():
         "roofline_trace": roof_trace,
     }
 
+    # the light's visibility filtered by the same SVGF as a second channel
+    # (own history), batched with the AO channel in one call
+    hist_s = [torch.empty(HW, 4, device=dev) for _ in range(2)]
+    out_s = torch.empty(HW, device=dev)
+    work_s = torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device=dev)
+    n2 = 10
+    e2 = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(n2)]
+    for k, f in enumerate(range(args.warmup + args.steps - n2 - 2, args.warmup + args.steps)):
+        cur, prv = gb[f % 2], gb[(f + 1) % 2]
+        B.dhr_gbuffer(ctx, bvh, cams[f], cams[f - 1], W, H, cur["pos"], cur["nz"], cur["dz"], cur["mv"])
+        B.dhr_trace_visibility(ctx, bvh, B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao,
+                                                        ao_radius=pr.ao_radius, n_shadow=pr.n_shadow, lights=lights),
+                               cur["pos"], cur["nz"], ao, sh)
+        first = k == 0
+        frs = [B.svgf_frame(W, H, pr.n_ao, ao, cur["pos"], cur["nz"], cur["dz"], cur["mv"], None if first else prv["pos"],
+                            None if first else prv["nz"], None if first else hist[(f + 1) % 2], hist[f % 2], out,
+                            B.pix_angle(cams[f], H), work=work),
+               B.svgf_frame(W, H, pr.n_shadow, sh[0], cur["pos"], cur["nz"], cur["dz"], cur["mv"],
+                            None if first else prv["pos"], None if first else prv["nz"],
+                            None if first else hist_s[(f + 1) % 2], hist_s[f % 2], out_s, B.pix_angle(cams[f], H),
+                            work=work_s)]
+        if k >= 2:
+            e2[k - 2][0].record()
+        B.dhr_svgf_filter(ctx, P, frs)
+        if k >= 2:
+            e2[k - 2][1].record()
+    torch.cuda.synchronize()
+    two_ms = sum(a.elapsed_time(b) for a, b in e2) / n2
+    line["svgf_ao_and_shadow"] = {"ms": two_ms, "mpix_s": 2 * HW / (two_ms / 1e3) / 1e6,
+                                  "vs_ao_only": two_ms / per["svgf"]}
+
     # wire form of the last frame: AO bytes + per-light bits (memory-bound)
     q8 = torch.empty(HW, dtype=torch.uint8, device=dev)
     m8 = torch.empty(HW, dtype=torch.uint8, device=dev)

@@ -305,3 +305,37 @@ def test_autograd_stack_matches_oracle_and_fits(B, ctx):
         losses.append(float(loss))
     print("sigma fit loss:", losses[0], "->", losses[-1], flush=True)
     assert losses[-1] < losses[0]
+
+
+@pytest.mark.parametrize("preset", ["room720", "terrain1080"])
+def test_shadow_channel_filter(B, ctx, preset):
+    """The light's visibility counts filtered by the same SVGF (own history),
+    batched with the AO channel in one call, against the oracle's filter of
+    the same counts."""
+    import torch
+    pr, fr = frames(preset, 3)
+    P, Po = B.svgf_params(), orc.svgf_params()
+    W, H, HW = pr.W, pr.H, pr.W * pr.H
+    h_ao = h_sh = None
+    for k, f in enumerate(fr):
+        prev = fr[k - 1] if k else None
+        ref_ao = orc_filter(Po, pr, f, prev, h_ao)
+        ref_sh = orc.svgf_filter(Po, W, H, pr.n_shadow, f["sh"][0], f["pos"], f["nz"], f["dz"], f["mv"],
+                                 prev["pos"] if prev else None, prev["nz"] if prev else None, h_sh, f["pix"])
+        geo = [dev(a) for a in (f["pos"], f["nz"], f["dz"], f["mv"])]
+        pv = [dev(prev["pos"]), dev(prev["nz"])] if prev else [None, None]
+        outs, frs = [], []
+        for n, cnt, h in ((pr.n_ao, f["ao"], h_ao), (pr.n_shadow, f["sh"][0], h_sh)):
+            hist = torch.empty(HW, 4, device="cuda")
+            out = torch.empty(HW, device="cuda")
+            work = torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device="cuda")
+            c_t = dev(np.ascontiguousarray(cnt))
+            h_t = dev(h) if h is not None else None
+            frs.append(B.svgf_frame(W, H, n, c_t, *geo, *pv, h_t, hist, out, float(f["pix"]), work=work))
+            outs.append((out, hist, work, c_t, h_t))   # the frames hold raw pointers: keep the tensors alive
+        B.dhr_svgf_filter(ctx, P, frs)
+        e_ao = np.abs(outs[0][0].cpu().numpy() - ref_ao["out"]).max()
+        e_sh = np.abs(outs[1][0].cpu().numpy() - ref_sh["out"]).max()
+        print(f"{preset} frame {k}: |ao - oracle| {e_ao:.2e}, |shadow - oracle| {e_sh:.2e}", flush=True)
+        assert e_ao <= ATOL and e_sh <= ATOL
+        h_ao, h_sh = ref_ao["hist_out"].astype(np.float32), ref_sh["hist_out"].astype(np.float32)
