@@ -269,6 +269,40 @@ def main():
     line["svgf_ao_and_shadow"] = {"ms": two_ms, "mpix_s": 2 * HW / (two_ms / 1e3) / 1e6,
                                   "vs_ao_only": two_ms / per["svgf"]}
 
+    # the hierarchy built on the device (linear BVH) and refitted, and the
+    # ray passes on it, against the host SAH build used above
+    tri_d = torch.from_numpy(np.ascontiguousarray(scene.tris, dtype=np.float32).reshape(-1, 9)).to(dev)
+    obj_d = torch.from_numpy(np.ascontiguousarray(scene.obj_id, dtype=np.uint32).view(np.int32)).to(dev)
+    B.dhr_build_bvh_device(ctx, tri_d, obj_d).close()
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    lbvh = B.dhr_build_bvh_device(ctx, tri_d, obj_d)
+    build_ms = (time.perf_counter() - tb) * 1e3
+    er = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    f = args.warmup + args.steps - 1
+    cur = gb[f % 2]
+    tp = B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao, ao_radius=pr.ao_radius, n_shadow=pr.n_shadow,
+                        lights=lights)
+    B.dhr_refit_bvh(ctx, lbvh, tri_d)
+    er[0].record()
+    for _ in range(5):
+        B.dhr_refit_bvh(ctx, lbvh, tri_d)
+    er[1].record()
+    for _ in range(5):
+        B.dhr_gbuffer(ctx, lbvh, cams[f], cams[f - 1], W, H, cur["pos"], cur["nz"], cur["dz"], cur["mv"])
+    er[2].record()
+    for _ in range(5):
+        B.dhr_trace_visibility(ctx, lbvh, tp, cur["pos"], cur["nz"], ao, sh)
+    er[3].record()
+    torch.cuda.synchronize()
+    li = lbvh.info()
+    line["bvh_device"] = {"build_ms": build_ms, "refit_ms": er[0].elapsed_time(er[1]) / 5,
+                          "gbuf_ms": er[1].elapsed_time(er[2]) / 5, "trace_ms": er[2].elapsed_time(er[3]) / 5,
+                          "nodes": li["n_nodes"], "depth": li["depth"],
+                          "host_sah_build_s": bvh_s, "host_sah_gbuf_ms": per["gbuf"], "host_sah_trace_ms": per["trace"]}
+    lbvh.close()
+    del tri_d, obj_d
+
     # wire form of the last frame: AO bytes + per-light bits (memory-bound)
     q8 = torch.empty(HW, dtype=torch.uint8, device=dev)
     m8 = torch.empty(HW, dtype=torch.uint8, device=dev)

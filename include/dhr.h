@@ -85,7 +85,7 @@ const char* dhr_version(void);
 typedef struct {
     uint32_t max_leaf;   /* triangles per leaf, 1..8 (default 4)               */
     uint32_t max_depth;  /* 8..32 (default 32); subtrees switch to median splits
-                            so the limit holds; traversal stacks are sized by it */
+                            so the limit holds (the traversal stack holds 64) */
     uint32_t sah_bins;   /* binned-SAH bins, 4..64 (default 16)                */
     uint32_t threads;    /* host build threads, 0 = hardware concurrency       */
 } dhr_bvh_opts;
@@ -107,7 +107,42 @@ typedef struct {
  * OOM (device allocation failed). */
 dhr_status dhr_build_bvh(dhr_ctx* ctx, const float* tris, const uint32_t* obj_id, uint32_t T,
                          const dhr_bvh_opts* opts, dhr_bvh** out);
+/* Builds the BVH on the device from device-resident triangles: a linear BVH
+ * over the Morton codes of the triangle centroids (Karras, HPG 2012), one
+ * triangle per leaf, in the node layout dhr_build_bvh produces, so every call
+ * taking a dhr_bvh accepts it and every query gives the same result as with
+ * any other valid hierarchy over the same triangles.  Its tree is of lower
+ * quality than the SAH build (traversal is slower) but it builds in
+ * milliseconds with the scene already in HBM, and it can be refitted.
+ *   tris    device float[T][3][3] (finite, 4-byte aligned; not retained)
+ *   obj_id  device uint32[T] or NULL (then the triangle index is the id)
+ *   out     receives the handle; free with dhr_bvh_destroy
+ * The kernels run on `stream`; the call waits for them (it reads back where
+ * each depth level starts) before returning.  Errors: INVALID_ARG (T == 0 or > 2^28, null or
+ * misaligned pointer), OOM, DEVICE, UNSUPPORTED (a path longer than the
+ * traversal stack; cannot happen for 30-bit codes, checked anyway). */
+dhr_status dhr_build_bvh_device(dhr_ctx* ctx, const float* tris, const uint32_t* obj_id, uint32_t T, dhr_bvh** out,
+                                dhr_stream stream);
+
+/* Refit of a device-built BVH after its triangles moved: same count, same
+ * order, same object ids.  Triangle records and boxes are recomputed from
+ * `tris` (device float[T][3][3]) and the topology is kept, so queries stay
+ * exact while traversal slows as the motion departs from the built layout.
+ * Asynchronous on `stream`; must not overlap work that reads the BVH.
+ * Errors: INVALID_ARG (null, misaligned, or a BVH built on the host). */
+dhr_status dhr_refit_bvh(dhr_ctx* ctx, dhr_bvh* bvh, const float* tris, dhr_stream stream);
+
 dhr_status dhr_bvh_get_info(const dhr_bvh* bvh, dhr_bvh_info* info);
+/* Copies the device records (to inspect, cache or serialise a hierarchy):
+ *   nodes  device buffer of info.n_nodes * 64 bytes: per node the x and y
+ *          slabs of child 0 (lo.x, hi.x, lo.y, hi.y), the same of child 1,
+ *          the z slabs of both (lo0, hi0, lo1, hi1) and the child references
+ *          (int: node index >= 0, leaf ~(first << 3 | count - 1)); node 0 is
+ *          the root
+ *   tris   device buffer of info.n_tris * 48 bytes in leaf order: v0 + input
+ *          index (bits), e1 + object id (bits), e2
+ * Asynchronous on `stream`.  Errors: INVALID_ARG (null pointer). */
+dhr_status dhr_bvh_export(dhr_ctx* ctx, const dhr_bvh* bvh, float* nodes, float* tris, dhr_stream stream);
 /* Frees the BVH's device memory (waits for work using it).  Valid before or
  * after the context that built it has been destroyed. */
 void dhr_bvh_destroy(dhr_bvh* bvh);

@@ -105,7 +105,7 @@ EXPORTS = ["dhr_create", "dhr_destroy", "dhr_last_error", "dhr_sync", "dhr_versi
            "dhr_bvh_get_info", "dhr_bvh_destroy", "dhr_gbuffer", "dhr_trace_visibility", "dhr_gbuffer_batch",
            "dhr_trace_visibility_batch", "dhr_svgf_default_params", "dhr_svgf_filter", "dhr_svgf_spatial_forward",
            "dhr_svgf_backward", "dhr_svgf_workspace_bytes", "dhr_philox4x32_10", "dhr_set_trace_counters",
-           "dhr_encode_frame"]
+           "dhr_encode_frame", "dhr_build_bvh_device", "dhr_refit_bvh", "dhr_bvh_export"]
 
 _lib = None
 
@@ -147,6 +147,9 @@ def load(path: str = LIB_PATH):
     L.dhr_philox4x32_10.argtypes = [vp, u32, u32, vp, vp, u64, vp]
     L.dhr_set_trace_counters.argtypes = [vp, vp]
     L.dhr_encode_frame.argtypes = [vp, vp, vp, vp, u32, u32, vp, u64, vp]
+    L.dhr_build_bvh_device.argtypes = [vp, vp, vp, u32, vp, vp]
+    L.dhr_refit_bvh.argtypes = [vp, vp, vp, vp]
+    L.dhr_bvh_export.argtypes = [vp, vp, vp, vp, vp]
     _lib = L
     return L
 
@@ -398,6 +401,30 @@ def dhr_philox4x32_10(ctx, key, ctr, out, stream=None):
     n = ctr.numel() // 4
     _check(ctx, load().dhr_philox4x32_10(ctx.handle, int(key[0]), int(key[1]), _ptr(ctr), _ptr(out), n,
                                          _stream(stream)), "dhr_philox4x32_10")
+
+
+def dhr_build_bvh_device(ctx: Context, tris, obj_id=None, stream=None) -> Bvh:
+    """tris: device float tensor [T, 9] (or [T, 3, 3]); obj_id: device uint32/int32 tensor [T] or None."""
+    t = tris.reshape(-1, 9)
+    h = C.c_void_p()
+    _check(ctx, load().dhr_build_bvh_device(ctx.handle, _ptr(t), _ptr(obj_id), t.shape[0], C.byref(h),
+                                            _stream(stream)), "dhr_build_bvh_device")
+    return Bvh(ctx, h)
+
+
+def dhr_bvh_export(ctx: Context, bvh: Bvh, stream=None):
+    """(nodes float32 [n_nodes, 16], tris float32 [n_tris, 12]) device copies of the records."""
+    info = bvh.info()
+    nodes = torch.empty(max(info["n_nodes"], 1), 16, device="cuda")
+    tris = torch.empty(info["n_tris"], 12, device="cuda")
+    _check(ctx, load().dhr_bvh_export(ctx.handle, bvh.handle, _ptr(nodes), _ptr(tris), _stream(stream)),
+           "dhr_bvh_export")
+    return nodes[: info["n_nodes"]], tris
+
+
+def dhr_refit_bvh(ctx: Context, bvh: Bvh, tris, stream=None):
+    _check(ctx, load().dhr_refit_bvh(ctx.handle, bvh.handle, _ptr(tris.reshape(-1, 9)), _stream(stream)),
+           "dhr_refit_bvh")
 
 
 def dhr_encode_frame(ctx, value=None, q=None, shadow_count=None, n_shadow=1, mask=None, stream=None):

@@ -352,6 +352,17 @@ dhr_status dhr_build_bvh(dhr_ctx* ctx, const float* tris, const uint32_t* obj_id
     return DHR_OK;
 }
 
+dhr_status dhr_bvh_export(dhr_ctx* ctx, const dhr_bvh* bvh, float* nodes, float* tris, dhr_stream stream) {
+    if (!ctx) return DHR_ERR_INVALID_ARG;
+    if (!bvh || !nodes || !tris) return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_bvh_export: null pointer");
+    dhr::DeviceGuard g(bvh->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(nodes, bvh->nodes, bvh->info.n_nodes * 64, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(tris, bvh->tris, bvh->info.n_tris * 48, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return dhr::set_error(ctx, DHR_ERR_DEVICE, "dhr_bvh_export: copy failed");
+    return DHR_OK;
+}
+
 dhr_status dhr_bvh_get_info(const dhr_bvh* bvh, dhr_bvh_info* info) {
     if (!bvh || !info) return DHR_ERR_INVALID_ARG;
     *info = bvh->info;
@@ -361,8 +372,9 @@ dhr_status dhr_bvh_get_info(const dhr_bvh* bvh, dhr_bvh_info* info) {
 void dhr_bvh_destroy(dhr_bvh* bvh) {
     if (!bvh) return;
     dhr::DeviceGuard g(bvh->device);
-    (void)hipFree(bvh->nodes);
-    (void)hipFree(bvh->tris);
+    for (void* p : {(void*)bvh->nodes, (void*)bvh->tris, (void*)bvh->child, (void*)bvh->parent, (void*)bvh->box,
+                    (void*)bvh->by_depth, (void*)bvh->bounds})
+        if (p) (void)hipFree(p);
     delete bvh;
 }
 

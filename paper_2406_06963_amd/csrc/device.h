@@ -95,7 +95,11 @@ __device__ __forceinline__ int find_job(const uint32_t* tile0, int n, uint32_t t
 }
 
 // ---------------------------------------------------------------- traversal
-constexpr int kStack = 32;  // the builder caps the depth at 32
+// Traversal stack depth: at most one entry is pushed per interior node on the
+// current path.  The host builder caps the depth at 32; device-built trees
+// have at most 64 interior nodes on a path (their common-prefix lengths grow
+// strictly from 0 to at most 63).
+constexpr int kStack = 64;
 
 struct Ray {
     float3 o, d;
@@ -235,7 +239,7 @@ constexpr int kDone = 0x7FFFFFFF;  // empty stack
 // child first by majority vote of the lanes that hit both.  Node and
 // triangle records are read once per wave at a uniform address (scalar
 // loads), and the stack is one LDS column per wave (`wstk`,
-// kStack entries: the builder caps the depth at kStack and at most one entry
+// kStack entries: no path holds more than kStack interior nodes and at most one entry
 // is pushed per level).  Child boxes lie inside the parent's box and the slab
 // test is monotone in the planes, so a lane visits every node its own ray
 // hits: each lane's result is that of a traversal of its own ray.  Lanes

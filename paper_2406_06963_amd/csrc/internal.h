@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/dhr.h"
 
@@ -25,6 +26,16 @@ struct dhr_bvh {
     float4* nodes = nullptr;
     float4* tris = nullptr;
     dhr_bvh_info info{};
+    // topology kept by the device build for refits (NULL for host builds):
+    // children of each internal node, parents of internal nodes and leaves,
+    // per-node boxes and arrival counters of the bottom-up pass
+    int2* child = nullptr;
+    int* parent = nullptr;        // [T - 1] internal, then [T] leaves
+    float* box = nullptr;         // [T - 1 + T][6]
+    uint32_t* by_depth = nullptr; // internal nodes ordered by depth, deepest level first
+    float* bounds = nullptr;      // reduction scratch
+    uint32_t n_tris = 0;
+    std::vector<uint32_t> level_off;  // by_depth ranges of the levels, deepest first
 };
 
 namespace dhr {

@@ -1,0 +1,161 @@
+"""The device BVH build and refit (needs an MI355X).
+
+* Structure: every triangle sits in exactly one leaf; every stored child box
+  holds its subtree's triangles; depth within the traversal stack.
+* Queries: visibility rays and the G-buffer on the device-built hierarchy
+  give the oracle's results, exactly as the host-built one does.
+* Refit: after an object moves, the refitted hierarchy answers like the
+  oracle on the moved scene.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2406_06963_amd import workloads as wl
+from oracle_inputs import frames, popcount64, scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    from paper_2406_06963_amd import binding
+    binding.load()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    return B.dhr_create(0)
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def device_bvh(B, ctx, tris, obj):
+    return B.dhr_build_bvh_device(ctx, dev(np.asarray(tris, np.float32).reshape(-1, 9)),
+                                  dev(np.asarray(obj, np.uint32).view(np.int32)))
+
+
+@pytest.mark.parametrize("name", ["spheres", "room"])
+def test_structure(B, ctx, name):
+    sc, _ = scene(name)
+    bvh = device_bvh(B, ctx, sc.tris, sc.obj_id)
+    info = bvh.info()
+    T = sc.n_tris
+    assert info["n_tris"] == T and info["n_nodes"] == T - 1 and info["max_leaf_size"] == 1
+    assert info["depth"] <= 65
+    nodes, recs = B.dhr_bvh_export(ctx, bvh)
+    nd = nodes.cpu().numpy().reshape(-1, 4, 4)
+    tr = recs.cpu().numpy().reshape(-1, 3, 4)
+    orig = tr[:, 0, 3].view(np.uint32)
+    assert np.array_equal(np.sort(orig), np.arange(T))
+    v0 = tr[:, 0, :3].astype(np.float64)
+    verts = np.stack([v0, v0 + tr[:, 1, :3], v0 + tr[:, 2, :3]], 1)
+    refs = nd[:, 3, :2].copy().view(np.int32)
+    seen = np.zeros(T, bool)
+
+    def bounds(ref):
+        if ref < 0:
+            k = (~ref) >> 3
+            assert not seen[k]
+            seen[k] = True
+            return verts[k].min(0), verts[k].max(0)
+        lo = np.full(3, np.inf)
+        hi = np.full(3, -np.inf)
+        for s in range(2):
+            clo, chi = bounds(int(refs[ref, s]))
+            r = nd[ref]
+            blo = np.array([r[s, 0], r[s, 2], r[2, 2 * s]])
+            bhi = np.array([r[s, 1], r[s, 3], r[2, 2 * s + 1]])
+            assert (blo <= clo).all() and (bhi >= chi).all(), (ref, s)
+            lo, hi = np.minimum(lo, clo), np.maximum(hi, chi)
+        return lo, hi
+
+    import sys
+    sys.setrecursionlimit(10000)
+    bounds(0)
+    assert seen.all()
+    # reported depth (levels, root and leaves included) equals the walked one
+    depth, level = 0, [0]
+    while level:
+        depth += 1
+        level = [int(c) for n in level for c in refs[n] if c >= 0]
+    assert info["depth"] == depth + 1
+
+
+@pytest.mark.parametrize("preset,n_ao,n_shadow", [("tiny", 8, 4), ("room720", 1, 1), ("terrain1080", 1, 2)])
+def test_queries_match_oracle(B, ctx, preset, n_ao, n_shadow):
+    import torch
+    pr, fr = frames(preset, 2)
+    sc, so = scene(pr.scene)
+    bvh = device_bvh(B, ctx, sc.tris, sc.obj_id)
+    f = fr[1]
+    kw = dict(f["trace_kw"], n_ao=n_ao, n_shadow=n_shadow)
+    L, HW = len(kw["lights"]), pr.W * pr.H
+    ao = torch.empty(HW, dtype=torch.uint8, device="cuda")
+    sh = torch.empty(L, HW, dtype=torch.uint8, device="cuda")
+    rb = torch.empty(1 + L, HW, dtype=torch.int64, device="cuda")
+    B.dhr_trace_visibility(ctx, bvh, B.trace_params(pr.W, pr.H, **kw), dev(f["pos"]), dev(f["nz"]), ao, sh, rb)
+    _, _, bits_o = orc.trace(so, orc.trace_params(pr.W, pr.H, **kw), f["pos"], f["nz"], ray_bits=True)
+    bad = popcount64(rb.cpu().numpy().view(np.uint64) ^ bits_o)
+    print(f"{preset}: {bad} rays differ on the device-built hierarchy", flush=True)
+    assert bad <= 1e-4 * HW * (n_ao + L * n_shadow)
+    # G-buffer: identical to the host-built hierarchy's (same closest hits)
+    host = B.dhr_build_bvh(ctx, sc.tris, sc.obj_id)
+    g1, g2 = B.gbuffer_tensors(pr.W, pr.H), B.gbuffer_tensors(pr.W, pr.H)
+    for bv, g in ((bvh, g1), (host, g2)):
+        B.dhr_gbuffer(ctx, bv, fr[1]["cam"], fr[0]["cam"], pr.W, pr.H, g["pos"], g["nz"], g["dz"], g["mv"])
+    for k in ("pos", "nz", "dz", "mv"):   # bitwise (pos.w of a miss is a NaN pattern)
+        assert torch.equal(g1[k].view(torch.int32), g2[k].view(torch.int32)), k
+
+
+def test_refit_after_motion(B, ctx):
+    import torch
+    pr, fr = frames("room720", 1)
+    sc, _ = scene("room")
+    tris = np.asarray(sc.tris, np.float32).reshape(-1, 9).copy()
+    bvh = device_bvh(B, ctx, tris, sc.obj_id)
+    # move two objects, one of them across the room
+    moved = tris.copy()
+    for oid, off in ((7, (0.3, 0.1, -0.2)), (40, (-6.0, 0.5, 4.0))):
+        m = np.asarray(sc.obj_id) == oid
+        moved[m] += np.tile(np.float32(off), 3)
+    B.dhr_refit_bvh(ctx, bvh, dev(moved))
+    so = orc.Scene(moved.reshape(-1, 3, 3), sc.obj_id)
+    f = fr[0]
+    pos, nz, dz, mv = orc.gbuffer(so, f["cam"], None, pr.W, pr.H)
+    kw = dict(f["trace_kw"], n_ao=2, n_shadow=1)
+    HW = pr.W * pr.H
+    ao = torch.empty(HW, dtype=torch.uint8, device="cuda")
+    sh = torch.empty(1, HW, dtype=torch.uint8, device="cuda")
+    rb = torch.empty(2, HW, dtype=torch.int64, device="cuda")
+    B.dhr_trace_visibility(ctx, bvh, B.trace_params(pr.W, pr.H, **kw), dev(pos), dev(nz), ao, sh, rb)
+    _, _, bits_o = orc.trace(so, orc.trace_params(pr.W, pr.H, **kw), pos, nz, ray_bits=True)
+    bad = popcount64(rb.cpu().numpy().view(np.uint64) ^ bits_o)
+    print(f"refit: {bad} rays differ", flush=True)
+    assert bad <= 1e-4 * HW * 3
+    g = B.gbuffer_tensors(pr.W, pr.H)
+    B.dhr_gbuffer(ctx, bvh, f["cam"], None, pr.W, pr.H, g["pos"], g["nz"], g["dz"], g["mv"])
+    ids = g["pos"].cpu().numpy()[:, 3].view(np.uint32)
+    assert (ids != orc.id_bits(pos)).mean() <= 1e-4
+
+
+def test_single_triangle_and_invalid(B, ctx):
+    import torch
+    tri = np.array([[-1, 0, -1, 1, 0, -1, 0, 0, 1]], np.float32)
+    bvh = B.dhr_build_bvh_device(ctx, dev(tri))
+    host = B.dhr_build_bvh(ctx, tri)
+    cam = wl.Camera(eye=(0.0, 3.0, 0.01), target=(0.0, 0.0, 0.0), fov_y=1.0)
+    g1, g2 = B.gbuffer_tensors(16, 16), B.gbuffer_tensors(16, 16)
+    for bv, g in ((bvh, g1), (host, g2)):
+        B.dhr_gbuffer(ctx, bv, cam, None, 16, 16, g["pos"], g["nz"], g["dz"], g["mv"])
+    assert torch.equal(g1["pos"].view(torch.int32), g2["pos"].view(torch.int32)) and (g1["nz"][:, 3] > 0).any()
+    with pytest.raises(B.DhrError):
+        B.dhr_build_bvh_device(ctx, torch.empty(0, 9, device="cuda"))
+    with pytest.raises(B.DhrError):
+        B.dhr_refit_bvh(ctx, host, dev(tri))          # host-built: no topology kept
