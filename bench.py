@@ -269,6 +269,12 @@ def main():
     line["svgf_ao_and_shadow"] = {"ms": two_ms, "mpix_s": 2 * HW / (two_ms / 1e3) / 1e6,
                                   "vs_ao_only": two_ms / per["svgf"]}
 
+    # the lighter filter (one level of the 3x3 kernel) beside the full one, each
+    # with its own history over the same noisy frames; both scored against a
+    # 64-ray AO estimate of the last frame
+    line["svgf_light"] = bench_light_filter(B, ctx, bvh, pr, cams, lights, gb, ao, sh, P,
+                                            range(max(1, args.warmup + args.steps - 16), args.warmup + args.steps))
+
     # the hierarchy built on the device (linear BVH) and refitted, and the
     # ray passes on it, against the host SAH build used above
     tri_d = torch.from_numpy(np.ascontiguousarray(scene.tris, dtype=np.float32).reshape(-1, 9)).to(dev)
@@ -328,6 +334,56 @@ def main():
     if args.cpu_frames > 0:
         line["cpu_baseline"] = cpu_baseline(pr, scene, cams, lights, args)
     print(json.dumps(line), flush=True)
+
+
+def bench_light_filter(B, ctx, bvh, pr, cams, lights, gb, ao, sh, P, frames):
+    import torch
+    W, H, HW = pr.W, pr.H, pr.W * pr.H
+    PL = B.svgf_params(levels=1, alpha=pr.alpha, kernel_width=3)
+    res = {}
+    for name, Pk in (("full", P), ("light", PL)):
+        hist = [torch.empty(HW, 4, device="cuda") for _ in range(2)]
+        out = torch.empty(HW, device="cuda")
+        work = torch.empty(B.dhr_svgf_workspace_bytes(W, H, Pk, 0) // 4, device="cuda")
+        ev = []
+        for k, f in enumerate(frames):
+            cur, prv = gb[f % 2], gb[(f + 1) % 2]
+            B.dhr_gbuffer(ctx, bvh, cams[f], cams[f - 1], W, H, cur["pos"], cur["nz"], cur["dz"], cur["mv"])
+            B.dhr_trace_visibility(ctx, bvh, B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao,
+                                                            ao_radius=pr.ao_radius, n_shadow=pr.n_shadow,
+                                                            lights=lights), cur["pos"], cur["nz"], ao, sh)
+            first = k == 0
+            fr = B.svgf_frame(W, H, pr.n_ao, ao, cur["pos"], cur["nz"], cur["dz"], cur["mv"],
+                              None if first else prv["pos"], None if first else prv["nz"],
+                              None if first else hist[(f + 1) % 2], hist[f % 2], out, B.pix_angle(cams[f], H),
+                              work=work)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e[0].record()
+            B.dhr_svgf_filter(ctx, Pk, [fr])
+            e[1].record()
+            if k >= 2:
+                ev.append(e)
+        torch.cuda.synchronize()
+        res[name] = {"ms": sum(a.elapsed_time(b) for a, b in ev) / len(ev), "out": out}
+    # reference: 64 AO rays per pixel of the last frame (another seed)
+    n_ref = 64
+    f = frames[-1]
+    cur = gb[f % 2]
+    ref = torch.empty(HW, dtype=torch.uint8, device="cuda")
+    sh1 = torch.empty(len(lights), HW, dtype=torch.uint8, device="cuda")
+    B.dhr_trace_visibility(ctx, bvh, B.trace_params(W, H, frame=f, seed=pr.seed + 1000, n_ao=n_ref,
+                                                    ao_radius=pr.ao_radius, n_shadow=1, lights=lights),
+                           cur["pos"], cur["nz"], ref, sh1)
+    valid = cur["nz"][:, 3] > 0
+    r = ref.float()[valid] / n_ref
+    raw = ao.float()[valid] / pr.n_ao
+    rmse = lambda x: float(torch.sqrt(((x - r) ** 2).mean()).item())
+    return {"kernel": "temporal + variance + one 3x3 a-trous level", "frames": len(frames),
+            "ms": res["light"]["ms"], "full_ms": res["full"]["ms"],
+            "mpix_s": HW / (res["light"]["ms"] / 1e3) / 1e6,
+            "rmse_vs_64spp": {"light": rmse(res["light"]["out"][valid]), "full": rmse(res["full"]["out"][valid]),
+                              "unfiltered_1spp": rmse(raw), "reference_own_noise_rms": float(
+                                  torch.sqrt((r * (1 - r) / n_ref).mean()).item())}}
 
 
 def bench_preset(B, ctx, name, steps, warmup=5):

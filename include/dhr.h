@@ -267,7 +267,8 @@ dhr_status dhr_trace_visibility_batch(dhr_ctx* ctx, const dhr_trace_job* jobs, u
  * neighbours, R = fallback_radius, weights w_z w_n of level 0.
  * A-trous level l (stride s = 2^l): g = sqrt of the 3x3 (1,2,1)/4 blur of
  * the variance over valid pixels; 5x5 taps q = p + s (a, b), h = B3(a) B3(b)
- * with B3 = (1,4,6,4,1)/16; w = 1 at the centre, else
+ * with B3 = (1,4,6,4,1)/16 (kernel_width 3: 3x3 taps, h = K(a) K(b) with
+ * K = (1,2,1)/4); w = 1 at the centre, else
  *   w_z = exp(-|z_p - z_q| / (sigma_z |s (a dz.x + b dz.y)| + eps_z_rel z_p))
  *   w_n = max(0, min(1, n_p . n_q))^sigma_n   (0 when the dot is <= 0)
  *   w_l = exp(-|c_p - c_q| / (sigma_l g + eps_l))
@@ -292,6 +293,10 @@ typedef struct {
     uint32_t fallback_radius; /* 0..3 (3) */
     uint32_t feedback_level;  /* < levels (0) */
     float history_cap;        /* >= 1 (255) */
+    uint32_t kernel_width;    /* 5: B3 spline taps (default); 3: (1,2,1)/4 taps,
+                                 the lighter variant (one level of a smaller
+                                 kernel, Section 3.3's outlook); the adjoint
+                                 takes 5 only */
 } dhr_svgf_params;
 
 /* Fills the defaults above. */
@@ -339,7 +344,9 @@ dhr_status dhr_svgf_spatial_forward(dhr_ctx* ctx, const dhr_svgf_params* params,
  *   grad_sigma device float[3][levels] receives dL/d (sigma_z, sigma_n,
  *             sigma_l), summed over all frames (overwritten; deterministic)
  * Kinks take the subgradient 0.  No gradient flows into z, normals or the
- * history.  work: dhr_svgf_workspace_bytes(W,H,p,1) bytes per frame. */
+ * history.  work: dhr_svgf_workspace_bytes(W,H,p,1) bytes per frame.
+ * Errors: INVALID_ARG (bad params, sizes or buffers), UNSUPPORTED
+ * (kernel_width 3: the adjoint covers the 5x5 kernel only). */
 typedef struct {
     uint32_t W, H;
     const float* save;          /* from the forward call with the same params */

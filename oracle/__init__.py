@@ -56,7 +56,7 @@ class SvgfParams(C.Structure):
                 ("cos_normal_min", C.c_float), ("plane_px", C.c_float),
                 ("use_obj_id", C.c_int32), ("var_min_history", C.c_int32),
                 ("fallback_radius", C.c_int32), ("feedback_level", C.c_int32),
-                ("history_cap", C.c_double)]
+                ("history_cap", C.c_double), ("kernel_width", C.c_int32)]
 
 
 def lib():
@@ -235,7 +235,7 @@ def trace(scene: Scene, params: TraceParams, pos, nz, pix_list=None, ray_bits=Fa
 def svgf_params(levels=5, alpha=0.2, alpha_moments=0.2, sigma_z=1.0, sigma_n=128.0, sigma_l=4.0,
                 eps_z_rel=1e-4, eps_l=1e-4, cos_normal_min=0.9, plane_px=4.0, use_obj_id=1,
                 var_min_history=4, fallback_radius=3, feedback_level=0, history_cap=255.0,
-                fp32=True) -> SvgfParams:
+                kernel_width=5, fp32=True) -> SvgfParams:
     """Defaults of the filter.  With fp32=True every continuous constant is
     first rounded to fp32 (the values the GPU path receives)."""
     r = (lambda v: float(np.float32(v))) if fp32 else float
@@ -250,6 +250,7 @@ def svgf_params(levels=5, alpha=0.2, alpha_moments=0.2, sigma_z=1.0, sigma_n=128
     p.cos_normal_min, p.plane_px = cos_normal_min, plane_px
     p.use_obj_id, p.var_min_history, p.fallback_radius = use_obj_id, var_min_history, fallback_radius
     p.feedback_level, p.history_cap = feedback_level, float(history_cap)
+    p.kernel_width = kernel_width
     return p
 
 

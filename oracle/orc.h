@@ -61,6 +61,7 @@ typedef struct {
     float cos_normal_min, plane_px;   /* decision thresholds (fp32 decisions) */
     int32_t use_obj_id, var_min_history, fallback_radius, feedback_level;
     double history_cap;
+    int32_t kernel_width;   /* 5: B3 spline taps; 3: (1,2,1)/4 taps */
 } orc_svgf_params;
 
 /* ---- counter-based RNG: Philox4x32-10 (Salmon et al., SC'11) ---- */

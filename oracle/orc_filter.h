@@ -20,6 +20,12 @@ namespace orc {
 const double kH1[5] = {1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16};
 const double kK1[3] = {0.25, 0.5, 0.25};
 
+// The a-trous kernel: radius 2 with B3 taps (kernel_width 5), or radius 1
+// with (1, 2, 1) / 4 taps (kernel_width 3: the lighter variant, one smaller
+// kernel, that Section 3.3 anticipates).
+inline int kernel_radius(const orc_svgf_params& P) { return P.kernel_width == 3 ? 1 : 2; }
+inline double kernel_tap(int R, int a) { return R == 2 ? kH1[a + 2] : kK1[a + 1]; }
+
 // ---- forward-mode dual numbers (value, tangent) ----
 struct Dual {
     double v, d;
@@ -100,13 +106,14 @@ void atrous_level(const orc_svgf_params& P, int W, int H, int level, const T* cv
             T g = dsqrt(G / T(sk));
             T cp = cv[2 * p];
             T D(0.0), Sc(0.0), Sv(0.0);
-            for (int b = -2; b <= 2; ++b)
-                for (int a = -2; a <= 2; ++a) {
+            const int R = kernel_radius(P);
+            for (int b = -R; b <= R; ++b)
+                for (int a = -R; a <= R; ++a) {
                     int qx = x + s * a, qy = y + s * b;
                     if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
                     int64_t q = (int64_t)qy * W + qx;
                     if (!valid_px(nz, q)) continue;
-                    double h = kH1[a + 2] * kH1[b + 2];
+                    double h = kernel_tap(R, a) * kernel_tap(R, b);
                     T w(1.0);
                     if (a != 0 || b != 0) {
                         w = weight_z(nz[4 * p + 3], nz[4 * q + 3], dz[2 * p], dz[2 * p + 1], a, b, s, sz, P.eps_z_rel) *

@@ -21,8 +21,8 @@ extern "C" {
 
 void orc_svgf_spatial_vjp(const orc_svgf_params* P, int W, int H, const double* cv_in, const float* nz,
                           const float* dz, const double* grad_out, double* grad_cv, double* grad_sigma) {
-    using orc::kH1;
     using orc::kK1;
+    const int R = orc::kernel_radius(*P), KW = 2 * R + 1;
     const int64_t HW = (int64_t)W * H;
     const int L = P->levels;
     // forward, keeping every level's input
@@ -62,9 +62,9 @@ void orc_svgf_spatial_vjp(const orc_svgf_params* P, int W, int H, const double* 
                 // weights and normaliser
                 double D = 0.0, Sc = 0.0, Sv = 0.0;
                 double wt[25];
-                for (int b = -2; b <= 2; ++b)
-                    for (int a = -2; a <= 2; ++a) {
-                        int t = (b + 2) * 5 + (a + 2);
+                for (int b = -R; b <= R; ++b)
+                    for (int a = -R; a <= R; ++a) {
+                        int t = (b + R) * KW + (a + R);
                         wt[t] = -1.0;
                         int qx = x + s * a, qy = y + s * b;
                         if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
@@ -77,20 +77,20 @@ void orc_svgf_spatial_vjp(const orc_svgf_params* P, int W, int H, const double* 
                                 orc::weight_n<double>(nz + 4 * p, nz + 4 * q, sn) *
                                 orc::weight_l<double>(cp, cv[2 * q], g, sl, P->eps_l);
                         wt[t] = w;
-                        double h = kH1[a + 2] * kH1[b + 2];
+                        double h = orc::kernel_tap(R, a) * orc::kernel_tap(R, b);
                         D += h * w;
                         Sc += h * w * cv[2 * q];
                         Sv += h * h * w * w * cv[2 * q + 1];
                     }
                 const double cpr = Sc / D, vpr = Sv / (D * D);
                 double gbar = 0.0;
-                for (int b = -2; b <= 2; ++b)
-                    for (int a = -2; a <= 2; ++a) {
-                        int t = (b + 2) * 5 + (a + 2);
+                for (int b = -R; b <= R; ++b)
+                    for (int a = -R; a <= R; ++a) {
+                        int t = (b + R) * KW + (a + R);
                         const double w = wt[t];
                         if (w < 0.0) continue;
                         int64_t q = (int64_t)(y + s * b) * W + (x + s * a);
-                        const double h = kH1[a + 2] * kH1[b + 2];
+                        const double h = orc::kernel_tap(R, a) * orc::kernel_tap(R, b);
                         const double cq = cv[2 * q], vq = cv[2 * q + 1];
                         // direct dependence of c' on c_q and of v' on v_q
                         cbar[q] += ab * h * w / D;

@@ -79,7 +79,7 @@ class dhr_svgf_params(C.Structure):
                 ("sigma_l", C.c_float * MAX_LEVELS), ("eps_z_rel", C.c_float), ("eps_l", C.c_float),
                 ("cos_normal_min", C.c_float), ("plane_px", C.c_float), ("use_obj_id", C.c_uint32),
                 ("var_min_history", C.c_uint32), ("fallback_radius", C.c_uint32),
-                ("feedback_level", C.c_uint32), ("history_cap", C.c_float)]
+                ("feedback_level", C.c_uint32), ("history_cap", C.c_float), ("kernel_width", C.c_uint32)]
 
 
 class dhr_svgf_frame(C.Structure):

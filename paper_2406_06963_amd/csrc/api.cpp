@@ -79,6 +79,7 @@ void dhr_svgf_default_params(dhr_svgf_params* p) {
     p->fallback_radius = 3;
     p->feedback_level = 0;
     p->history_cap = 255.0f;
+    p->kernel_width = 5;
 }
 
 }  // extern "C"

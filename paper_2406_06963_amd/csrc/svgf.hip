@@ -236,7 +236,7 @@ __global__ __launch_bounds__(kSvgfBlock) void prefilter_kernel(const SvgfBatch B
 // A-trous level at a large stride: every tap read from global memory (each
 // tap of a wave is a contiguous row segment, so loads stay coalesced; LDS
 // sub-image tiles would touch one cache line per pixel at these strides).
-template <int LEVEL>
+template <int LEVEL, int KR>
 __global__ __launch_bounds__(kSvgfBlock) void atrous_direct_kernel(const SvgfBatch B, const SvgfK P) {
     constexpr int s = 1 << LEVEL;
     const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
@@ -262,12 +262,13 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_direct_kernel(const SvgfBat
     const float2 dzp = D.dz[i];
     const float3 np = f3(n4);
     const float sz = P.sz[LEVEL], sn = P.sn[LEVEL], eps_zp = P.eps_z * n4.w;
-    float Dn = 0.140625f, Sc = 0.0f, Sv = 0.140625f * 0.140625f * cvp.y;
+    float Dn = centre_h<KR>, Sc = 0.0f, Sv = centre_h<KR> * centre_h<KR> * cvp.y;
 #pragma unroll
-    for (int tp = 0; tp < 12; ++tp) {
-        const int a = (tp + 13) % 5 - 2, b = (tp + 13) / 5 - 2;
+    for (int tp = 0; tp < half_taps<KR>; ++tp) {
+        int a, b;
+        tap_ab<KR>(tp, a, b);
         const float kz = depth_coef(dzp, a, b, s, sz, eps_zp);
-        const float h = b3(a) * b3(b);
+        const float h = hk<KR>(a) * hk<KR>(b);
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
             const int qx = x + (m ? -s * a : s * a), qy = y + (m ? -s * b : s * b);
@@ -293,15 +294,16 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_direct_kernel(const SvgfBat
 }
 
 // A-trous level LEVEL (stride s = 2^LEVEL; used for level 0).  The pixels
-// congruent to (ox, oy) mod s form a sub-image on which the dilated 5x5 stencil is dense:
-// a workgroup owns a 16 x 16 block of one sub-image and stages its 20 x 20
+// congruent to (ox, oy) mod s form a sub-image on which the dilated stencil
+// (5x5, or 3x3 for KR = 1) is dense:
+// a workgroup owns a 16 x 16 block of one sub-image and stages its 20 x 20 (18 x 18)
 // neighbourhood (geometry and (c, var)) in LDS once, so the 25 taps read LDS
 // instead of global memory.  Tile t of a frame: super-tile t / s^2 (16s x 16s
 // image pixels), sub-image t % s^2.
-template <int LEVEL>
+template <int LEVEL, int KR>
 __global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, const SvgfK P) {
     constexpr int s = 1 << LEVEL;
-    constexpr int T = kSvgfTile, TW = kSvgfTile + 4;
+    constexpr int T = kSvgfTile, TW = kSvgfTile + 2 * KR;
     __shared__ float4 s_nz[TW * TW];
     __shared__ float2 s_cv[TW * TW];
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -315,7 +317,7 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, c
     const float2* __restrict__ src = level_buf(D, LEVEL);
     stage_tile<TW * TW>(
         [&](int e) {
-            const int qx = bx + s * (e % TW - 2), qy = by + s * (e / TW - 2);
+            const int qx = bx + s * (e % TW - KR), qy = by + s * (e / TW - KR);
             Staged r{make_float4(0.0f, 0.0f, 0.0f, 0.0f), make_float2(0.0f, 0.0f)};
             if (qx >= 0 && qx < W && qy >= 0 && qy < H) {
                 const size_t q = (size_t)qy * W + qx;
@@ -334,7 +336,7 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, c
     const int x = bx + s * li, y = by + s * lj;
     if (x >= W || y >= H) return;
     const size_t i = (size_t)y * W + x;
-    const int c = (lj + 2) * TW + (li + 2);
+    const int c = (lj + KR) * TW + (li + KR);
     const bool last = LEVEL + 1 == (int)P.levels;
     const float4 n4 = s_nz[c];
     if (!(n4.w > 0.0f)) {
@@ -369,13 +371,14 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, c
     const float3 np = f3(n4);
     const float sz = P.sz[LEVEL], sn = P.sn[LEVEL], eps_zp = P.eps_z * n4.w;
     // centre tap: w = 1
-    float Dn = 0.140625f, Sc = 0.0f, Sv = 0.140625f * 0.140625f * cvp.y;
+    float Dn = centre_h<KR>, Sc = 0.0f, Sv = centre_h<KR> * centre_h<KR> * cvp.y;
 #pragma unroll
-    for (int tp = 0; tp < 12; ++tp) {
-        // the 12 taps after (0, 0) in raster order, and their mirrors
-        const int a = (tp + 13) % 5 - 2, b = (tp + 13) / 5 - 2;
+    for (int tp = 0; tp < half_taps<KR>; ++tp) {
+        // the taps after (0, 0) in raster order, and their mirrors
+        int a, b;
+        tap_ab<KR>(tp, a, b);
         const float kz = depth_coef(dzp, a, b, s, sz, eps_zp);
-        const float h = b3(a) * b3(b);
+        const float h = hk<KR>(a) * hk<KR>(b);
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
             const int e = m ? c - b * TW - a : c + b * TW + a;
@@ -397,13 +400,13 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, c
 // A-trous level LEVEL >= 1 (stride s = 2^LEVEL) on row classes: a workgroup
 // owns 64 consecutive pixels of 4 rows that are s apart (rows congruent mod
 // s), so every tap of the dilated 5x5 stencil falls on 8 staged rows of
-// 64 + 4s consecutive pixels.  Staging reads whole row segments (coalesced at
+// 64 + 4s consecutive pixels (3x3 stencil, KR = 1: 6 rows of 64 + 2s).  Staging reads whole row segments (coalesced at
 // any stride) and each staged pixel serves up to 20 taps from LDS.  Tile t of
 // a frame: column block t % tx, then row class, then block of 4s rows.
-template <int LEVEL>
+template <int LEVEL, int KR>
 __global__ __launch_bounds__(kSvgfBlock) void atrous_rows_kernel(const SvgfBatch B, const SvgfK P) {
     constexpr int s = 1 << LEVEL;
-    constexpr int CW = kRowsTX + 4 * s, CH = kRowsTY + 4, GW = kRowsTX + 2;
+    constexpr int CW = kRowsTX + 2 * KR * s, CH = kRowsTY + 2 * KR, GW = kRowsTX + 2;
     __shared__ float4 s_nz[CH * CW];
     __shared__ float2 s_cv[CH * CW];
     __shared__ float s_g[kRowsTY * 2 * GW];  // variance of the rows above and below each output row
@@ -418,7 +421,7 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_rows_kernel(const SvgfBatch
     const float2* __restrict__ src = level_buf(D, LEVEL);
     stage_tile<CH * CW>(
         [&](int e) {
-            const int qx = x0 - 2 * s + e % CW, qy = y0 + s * (e / CW - 2);
+            const int qx = x0 - KR * s + e % CW, qy = y0 + s * (e / CW - KR);
             Staged r{make_float4(0.0f, 0.0f, 0.0f, 0.0f), make_float2(0.0f, 0.0f)};
             if (qx >= 0 && qx < W && qy >= 0 && qy < H) {
                 const size_t q = (size_t)qy * W + qx;
@@ -445,7 +448,7 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_rows_kernel(const SvgfBatch
     const int x = x0 + li, y = y0 + s * lj;
     if (x >= W || y >= H) return;
     const size_t i = (size_t)y * W + x;
-    const int c = (lj + 2) * CW + 2 * s + li;
+    const int c = (lj + KR) * CW + KR * s + li;
     const bool last = LEVEL + 1 == (int)P.levels;
     const float4 n4 = s_nz[c];
     if (!(n4.w > 0.0f)) {
@@ -475,12 +478,13 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_rows_kernel(const SvgfBatch
     const float2 dzp = D.dz[i];
     const float3 np = f3(n4);
     const float sz = P.sz[LEVEL], sn = P.sn[LEVEL], eps_zp = P.eps_z * n4.w;
-    float Dn = 0.140625f, Sc = 0.0f, Sv = 0.140625f * 0.140625f * cvp.y;
+    float Dn = centre_h<KR>, Sc = 0.0f, Sv = centre_h<KR> * centre_h<KR> * cvp.y;
 #pragma unroll
-    for (int tp = 0; tp < 12; ++tp) {
-        const int a = (tp + 13) % 5 - 2, b = (tp + 13) / 5 - 2;
+    for (int tp = 0; tp < half_taps<KR>; ++tp) {
+        int a, b;
+        tap_ab<KR>(tp, a, b);
         const float kz = depth_coef(dzp, a, b, s, sz, eps_zp);
-        const float h = b3(a) * b3(b);
+        const float h = hk<KR>(a) * hk<KR>(b);
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
             const int e = m ? c - b * CW - s * a : c + b * CW + s * a;
@@ -501,17 +505,25 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_rows_kernel(const SvgfBatch
 // same tile), levels 1-5 row classes, deeper levels read taps directly.
 constexpr uint32_t kRowsMaxLevel = 5;
 
-void launch_atrous(uint32_t level, dim3 grid, hipStream_t s, const SvgfBatch& B, const SvgfK& K) {
+template <int KR>
+void launch_atrous_r(uint32_t level, dim3 grid, hipStream_t s, const SvgfBatch& B, const SvgfK& K) {
     switch (level) {
-        case 0: hipLaunchKernelGGL(atrous_kernel<0>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
-        case 1: hipLaunchKernelGGL(atrous_rows_kernel<1>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
-        case 2: hipLaunchKernelGGL(atrous_rows_kernel<2>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
-        case 3: hipLaunchKernelGGL(atrous_rows_kernel<3>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
-        case 4: hipLaunchKernelGGL(atrous_rows_kernel<4>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
-        case 5: hipLaunchKernelGGL(atrous_rows_kernel<5>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
-        case 6: hipLaunchKernelGGL(atrous_direct_kernel<6>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
-        default: hipLaunchKernelGGL(atrous_direct_kernel<7>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 0: hipLaunchKernelGGL((atrous_kernel<0, KR>), grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 1: hipLaunchKernelGGL((atrous_rows_kernel<1, KR>), grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 2: hipLaunchKernelGGL((atrous_rows_kernel<2, KR>), grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 3: hipLaunchKernelGGL((atrous_rows_kernel<3, KR>), grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 4: hipLaunchKernelGGL((atrous_rows_kernel<4, KR>), grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 5: hipLaunchKernelGGL((atrous_rows_kernel<5, KR>), grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        case 6: hipLaunchKernelGGL((atrous_direct_kernel<6, KR>), grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        default: hipLaunchKernelGGL((atrous_direct_kernel<7, KR>), grid, dim3(kSvgfBlock), 0, s, B, K); break;
     }
+}
+
+void launch_atrous(uint32_t level, dim3 grid, hipStream_t s, const SvgfBatch& B, const SvgfK& K) {
+    if (K.kw == 3)
+        launch_atrous_r<1>(level, grid, s, B, K);
+    else
+        launch_atrous_r<2>(level, grid, s, B, K);
 }
 
 // ------------------------------------------------------------------ host side
@@ -531,6 +543,8 @@ dhr_status check_params(dhr_ctx* ctx, const dhr_svgf_params* p, const char* what
     if (!(p->eps_z_rel > 0.0f) || !(p->eps_l > 0.0f) || !std::isfinite(p->eps_z_rel) || !std::isfinite(p->eps_l))
         return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: eps_z_rel and eps_l must be positive", what);
     if (p->fallback_radius > 3) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: fallback_radius > 3", what);
+    if (p->kernel_width != 3 && p->kernel_width != 5)
+        return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: kernel_width = %u is neither 3 nor 5", what, p->kernel_width);
     if (p->feedback_level >= p->levels) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: feedback_level >= levels", what);
     if (!(p->history_cap >= 1.0f) || !std::isfinite(p->history_cap))
         return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: history_cap < 1", what);
@@ -562,6 +576,7 @@ SvgfK kparams(const dhr_svgf_params* p) {
     k.R = p->fallback_radius;
     k.fb_level = p->feedback_level;
     k.cap = p->history_cap;
+    k.kw = p->kernel_width;
     return k;
 }
 

@@ -569,6 +569,8 @@ dhr_status dhr_svgf_backward(dhr_ctx* ctx, const dhr_svgf_params* params, const 
     if (!ctx) return DHR_ERR_INVALID_ARG;
     dhr_status st = svgf_check_params(ctx, params, "dhr_svgf_backward");
     if (st != DHR_OK) return st;
+    if (params->kernel_width != 5)
+        return set_error(ctx, DHR_ERR_UNSUPPORTED, "dhr_svgf_backward: the adjoint takes kernel_width 5 only");
     if (!grad_sigma || (n_frames && !frames))
         return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_backward: null pointer");
     const uint32_t L = params->levels;

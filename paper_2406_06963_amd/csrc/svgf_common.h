@@ -18,6 +18,7 @@ struct SvgfK {
     float eps_z, eps_l, cos_min, plane_px;
     uint32_t use_obj, var_min_h, R, fb_level;
     float cap;
+    uint32_t kw;  // a-trous kernel width, 5 or 3
 };
 
 struct SvgfDesc {
@@ -120,6 +121,22 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {
 // 1-D taps: B3 spline (1,4,6,4,1)/16 and the (1,2,1)/4 variance prefilter
 __device__ __forceinline__ float b3(int a) { return a == 0 ? 0.375f : (a == 1 || a == -1 ? 0.25f : 0.0625f); }
 __device__ __forceinline__ float k3(int a) { return a == 0 ? 0.5f : 0.25f; }
+
+// The a-trous stencil of radius KR (2: 5x5 B3 taps, 1: 3x3 (1,2,1)/4 taps).
+// Tap tp < half_taps<KR> is the tp-th tap after the centre in raster order;
+// its mirror (-a, -b) is the matching tap before the centre.
+template <int KR>
+__device__ __forceinline__ float hk(int a) { return KR == 2 ? b3(a) : k3(a); }
+template <int KR>
+constexpr int half_taps = ((2 * KR + 1) * (2 * KR + 1) - 1) / 2;
+template <int KR>
+constexpr float centre_h = KR == 2 ? 0.140625f : 0.25f;  // h(0, 0)
+template <int KR>
+__device__ __forceinline__ void tap_ab(int tp, int& a, int& b) {
+    const int idx = tp + half_taps<KR> + 1;
+    a = idx % (2 * KR + 1) - KR;
+    b = idx / (2 * KR + 1) - KR;
+}
 
 // All three edge-stopping terms as one power of two:
 //   w = exp2(kz |z_p - z_q| + ke |c_p - c_q| + sigma_n log2(n_p . n_q))

@@ -33,14 +33,14 @@ def test_struct_sizes_match_the_header():
     assert ctypes.sizeof(B.dhr_light) == 24
     assert ctypes.sizeof(B.dhr_trace_params) == 40 + 8 * 24 + 4
     assert ctypes.sizeof(B.dhr_camera) == 28
-    assert ctypes.sizeof(B.dhr_svgf_params) == 4 * (3 + 24 + 4 + 4 + 1)
+    assert ctypes.sizeof(B.dhr_svgf_params) == 4 * (3 + 24 + 4 + 4 + 1 + 1)
 
 
 def test_host_only_calls():
     from paper_2406_06963_amd import binding as B
     assert B.dhr_version().startswith("dhr")
     p = B.svgf_params()
-    assert p.levels == 5 and abs(p.alpha - 0.2) < 1e-7 and p.sigma_n[0] == 128.0
+    assert p.levels == 5 and abs(p.alpha - 0.2) < 1e-7 and p.sigma_n[0] == 128.0 and p.kernel_width == 5
     assert B.dhr_svgf_workspace_bytes(1920, 1080, p, 0) == 2 * 1920 * 1080 * 8 + 1920 * 1080 * 4
     # creating a context without a device fails cleanly with a status
     import torch

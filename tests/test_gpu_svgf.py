@@ -2,7 +2,8 @@
 
 * Filtered AO within 1e-4 absolute of the oracle when both are fed the same
   noisy AO, G-buffer and (teacher-forced) history, on every workload at full
-  size; history lengths identical.
+  size; history lengths identical.  The same for the lighter variant (one
+  level of the 3x3 kernel), and every level count for both kernel widths.
 * Free-running (each side keeps its own history): fraction of pixels beyond
   1e-4 reported and bounded.
 * Adjoint: gradients w.r.t. (c, var) and the 15 sigmas within rel 1e-3 of the
@@ -58,10 +59,12 @@ def orc_filter(Po, pr, f, prev, hist_in):
                            prev["pos"] if prev else None, prev["nz"] if prev else None, hist_in, f["pix"])
 
 
-@pytest.mark.parametrize("preset,n", [("tiny", 8), ("room720", 3), ("terrain1080", 3)])
-def test_filter_parity_teacher_forced(B, ctx, preset, n):
+@pytest.mark.parametrize("preset,n,light", [("tiny", 8, False), ("room720", 3, False), ("terrain1080", 3, False),
+                                            ("tiny", 8, True), ("terrain1080", 3, True)])
+def test_filter_parity_teacher_forced(B, ctx, preset, n, light):
     pr, fr = frames(preset, n)
-    P, Po = B.svgf_params(), orc.svgf_params()
+    kw = dict(levels=1, kernel_width=3) if light else {}
+    P, Po = B.svgf_params(**kw), orc.svgf_params(**kw)
     hist_in = None
     worst = 0.0
     for k, f in enumerate(fr):
@@ -74,7 +77,7 @@ def test_filter_parity_teacher_forced(B, ctx, preset, n):
         assert np.array_equal(hist[:, 3], ref["hist_out"][:, 3].astype(np.float32)), k
         assert np.abs(hist[:, :3] - ref["hist_out"][:, :3]).max() <= ATOL, k
         hist_in = ref["hist_out"].astype(np.float32)          # teacher forcing: the oracle's history
-    print(f"{preset}: max |out - oracle| over {n} frames = {worst:.2e}", flush=True)
+    print(f"{preset}{' light' if light else ''}: max |out - oracle| over {n} frames = {worst:.2e}", flush=True)
 
 
 def test_filter_free_running(B, ctx):
@@ -136,6 +139,14 @@ def gpu_spatial_backward(B, ctx, P, W, H, cv, nz, dz, go, reps=1):
     return out.cpu().numpy(), res
 
 
+def test_backward_rejects_the_light_kernel(B, ctx):
+    pr, f, cv = _spatial_case("tiny", 1, jitter=False)
+    P = B.svgf_params(levels=1, kernel_width=3)
+    go = np.zeros(pr.W * pr.H, np.float32)
+    with pytest.raises(B.DhrError):
+        gpu_spatial_backward(B, ctx, P, pr.W, pr.H, cv, f["nz"], f["dz"], go)
+
+
 @pytest.mark.parametrize("preset,frame", [("tiny", 3), ("room720", 1)])
 def test_backward_parity(B, ctx, preset, frame):
     pr, f, cv = _spatial_case(preset, frame)
@@ -158,18 +169,18 @@ def test_backward_parity(B, ctx, preset, frame):
     assert (err <= 1e-3 * np.abs(gs_o) + 1e-8).all(), err / (np.abs(gs_o) + 1e-8)
 
 
-@pytest.mark.parametrize("levels", [1, 3, 6, 8])
-def test_spatial_forward_every_level(B, ctx, levels):
+@pytest.mark.parametrize("levels,kw", [(1, 5), (3, 5), (6, 5), (8, 5), (1, 3), (3, 3), (8, 3)])
+def test_spatial_forward_every_level(B, ctx, levels, kw):
     """Level counts 1..8 reach every kernel form (dense tile at level 0, row
     classes at strides 2..32, direct taps and the separate prefilter at 64 and
-    128): the output and every saved level's (c, var) on valid pixels match
-    the oracle."""
+    128), for the 5x5 and the 3x3 kernel: the output and every saved level's
+    (c, var) on valid pixels match the oracle."""
     import torch
     pr, f, cv = _spatial_case("room720", 1, jitter=False)
     W, H = pr.W, pr.H
     sz, sn, sl = _sigmas(levels, 11)
-    P = B.svgf_params(levels=levels, sigma_z=sz, sigma_n=sn, sigma_l=sl)
-    Po = orc.svgf_params(levels=levels, sigma_z=sz, sigma_n=sn, sigma_l=sl)
+    P = B.svgf_params(levels=levels, sigma_z=sz, sigma_n=sn, sigma_l=sl, kernel_width=kw)
+    Po = orc.svgf_params(levels=levels, sigma_z=sz, sigma_n=sn, sigma_l=sl, kernel_width=kw)
     out = torch.empty(W * H, device="cuda")
     save = torch.empty(levels, W * H, 2, device="cuda")
     work = torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device="cuda")
@@ -179,7 +190,7 @@ def test_spatial_forward_every_level(B, ctx, levels):
     err = np.abs(out.cpu().numpy() - ref).max()
     valid = f["nz"].reshape(-1, 4)[:, 3] > 0
     lv = np.abs(save.cpu().numpy()[:, valid] - ref_save[:, valid]).max(axis=(1, 2))
-    print(f"levels {levels}: max |out - oracle| {err:.2e}; per saved level {lv}", flush=True)
+    print(f"levels {levels} width {kw}: max |out - oracle| {err:.2e}; per saved level {lv}", flush=True)
     assert err <= ATOL and (lv <= ATOL).all()
 
 
@@ -252,7 +263,7 @@ def test_svgf_invalid_arguments(B, ctx):
     t = [dev(a) for a in (f["ao"], f["pos"], f["nz"], f["dz"], f["mv"])]
     good = B.svgf_frame(W, H, 1, *t, None, None, None, hist, out, float(f["pix"]), work=work)
     for bad in (dict(levels=0), dict(levels=9), dict(sigma_z=0.0), dict(sigma_l=-1.0), dict(sigma_n=-2.0),
-                dict(feedback_level=7), dict(alpha=0.0)):
+                dict(feedback_level=7), dict(alpha=0.0), dict(kernel_width=4), dict(kernel_width=7)):
         with pytest.raises(B.DhrError):
             B.dhr_svgf_filter(ctx, B.svgf_params(**bad), [good])
     nao0 = B.svgf_frame(W, H, 0, *t, None, None, None, hist, out, float(f["pix"]), work=work)

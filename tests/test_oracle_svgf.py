@@ -16,12 +16,19 @@ an iterated edge-aware spatial kernel driven by that variance.
   the spatial fallback on a flat patch is the variance of the pooled moments;
 * T13 the adjoint agrees with a forward-mode (dual number) JVP in the
       dot-product test and with central differences.
+
+The lighter variant (one level of a 3x3 (1,2,1)/4 kernel, the outlook of
+Section 3.3) is pinned the same way: constant image, unit weights against
+scipy's convolution, one level against a hand-written 3x3 sum, and its
+adjoint by the dot-product test.
 """
 import numpy as np
 import pytest
 from scipy import ndimage
 
 H1 = np.array([1, 4, 6, 4, 1]) / 16.0
+K1 = np.array([1, 2, 1]) / 4.0
+TAPS = {5: H1, 3: K1}
 
 
 def _geom(W, H, seed, z_const=None, cone=0.3, invalid_frac=0.0):
@@ -38,25 +45,28 @@ def _geom(W, H, seed, z_const=None, cone=0.3, invalid_frac=0.0):
 
 # ---------------------------------------------------------------- a-trous pins
 
-def test_constant_image_unchanged(orc):
+@pytest.mark.parametrize("kw", [5, 3])
+def test_constant_image_unchanged(orc, kw):
     W, H = 37, 29
     nz, dz = _geom(W, H, 1, invalid_frac=0.1)
     rng = np.random.default_rng(2)
     cv = np.column_stack([np.full(W * H, 0.37), rng.uniform(0, 0.2, W * H)])
-    P = orc.svgf_params(levels=5)
+    P = orc.svgf_params(levels=5, kernel_width=kw)
     out = orc.svgf_spatial(P, W, H, cv, nz, dz)
     valid = nz[:, 3] > 0
     np.testing.assert_allclose(out[valid], 0.37, atol=1e-12)
     assert (out[~valid] == 1.0).all()
 
 
-def test_unit_weights_reduce_to_normalised_convolution(orc):
+@pytest.mark.parametrize("kw", [5, 3])
+def test_unit_weights_reduce_to_normalised_convolution(orc, kw):
     W, H = 45, 38
     nz, dz = _geom(W, H, 3, z_const=2.0, cone=0.2, invalid_frac=0.15)
     rng = np.random.default_rng(4)
     cv = np.column_stack([rng.random(W * H), rng.uniform(0.01, 0.3, W * H)])
     L = 4
-    P = orc.svgf_params(levels=L, sigma_z=1.0, sigma_n=0.0, sigma_l=1e300, fp32=False)
+    P = orc.svgf_params(levels=L, sigma_z=1.0, sigma_n=0.0, sigma_l=1e300, fp32=False, kernel_width=kw)
+    R = kw // 2
     valid = (nz[:, 3] > 0).reshape(H, W)
     m = valid.astype(np.float64)
     c = cv[:, 0].reshape(H, W).copy()
@@ -64,8 +74,8 @@ def test_unit_weights_reduce_to_normalised_convolution(orc):
     cur = cv.copy()
     for level in range(L):
         s = 1 << level
-        K = np.zeros((4 * s + 1, 4 * s + 1))
-        K[::s, ::s] = np.outer(H1, H1)
+        K = np.zeros((2 * R * s + 1, 2 * R * s + 1))
+        K[::s, ::s] = np.outer(TAPS[kw], TAPS[kw])
         den = ndimage.convolve(m, K, mode="constant")
         c_ref = ndimage.convolve(c * m, K, mode="constant") / den
         v_ref = ndimage.convolve(v * m, K * K, mode="constant") / den ** 2
@@ -73,6 +83,49 @@ def test_unit_weights_reduce_to_normalised_convolution(orc):
         np.testing.assert_allclose(nxt[:, 0].reshape(H, W)[valid], c_ref[valid], rtol=1e-12, atol=1e-12)
         np.testing.assert_allclose(nxt[:, 1].reshape(H, W)[valid], v_ref[valid], rtol=1e-12, atol=1e-14)
         c, v, cur = c_ref, v_ref, nxt
+
+
+def test_light_kernel_one_level_by_hand(orc):
+    # one level of the 3x3 kernel written out for a few pixels: prefilter g,
+    # the three stopping terms, then the weighted sums (stride 1)
+    W, H = 9, 7
+    nz, dz = _geom(W, H, 8, invalid_frac=0.1)
+    rng = np.random.default_rng(9)
+    cv = np.column_stack([rng.random(W * H), rng.uniform(0.01, 0.2, W * H)])
+    P = orc.svgf_params(levels=1, sigma_z=0.7, sigma_n=40.0, sigma_l=3.0, fp32=False, kernel_width=3)
+    out = orc.svgf_atrous(P, W, H, 0, cv, nz, dz)
+    ok = lambda x, y: 0 <= x < W and 0 <= y < H and nz[y * W + x, 3] > 0
+    for (x, y) in [(0, 0), (4, 3), (8, 6), (3, 0), (0, 5), (5, 5)]:
+        p = y * W + x
+        if not ok(x, y):
+            continue
+        G = sk = 0.0
+        for b in (-1, 0, 1):
+            for a in (-1, 0, 1):
+                if ok(x + a, y + b):
+                    k = K1[a + 1] * K1[b + 1]
+                    G += k * cv[(y + b) * W + x + a, 1]
+                    sk += k
+        g = np.sqrt(G / sk)
+        D = Sc = Sv = 0.0
+        for b in (-1, 0, 1):
+            for a in (-1, 0, 1):
+                if not ok(x + a, y + b):
+                    continue
+                q = (y + b) * W + x + a
+                w = 1.0
+                if (a, b) != (0, 0):
+                    zp, zq = float(nz[p, 3]), float(nz[q, 3])
+                    wz = np.exp(-abs(zp - zq) / (0.7 * abs(a * float(dz[p, 0]) + b * float(dz[p, 1])) + 1e-4 * zp))
+                    d = float(np.dot(nz[p, :3].astype(np.float64), nz[q, :3].astype(np.float64)))
+                    wn = min(d, 1.0) ** 40.0 if d > 0 else 0.0
+                    wl = np.exp(-abs(cv[p, 0] - cv[q, 0]) / (3.0 * g + 1e-4))
+                    w = wz * wn * wl
+                h = K1[a + 1] * K1[b + 1]
+                D += h * w
+                Sc += h * w * cv[q, 0]
+                Sv += h * h * w * w * cv[q, 1]
+        np.testing.assert_allclose(out[p], [Sc / D, Sv / D ** 2], rtol=1e-12, atol=1e-15)
 
 
 def test_edge_stopping_blocks_across_depth_edge(orc):
@@ -229,15 +282,16 @@ def _vjp_case(W, H, L, seed):
     return nz, dz, cv, P
 
 
-def orc_params(L, rng):
+def orc_params(L, rng, kernel_width=5):
     import oracle
     return oracle.svgf_params(levels=L, sigma_z=rng.uniform(0.5, 2, L), sigma_n=rng.uniform(16, 128, L),
-                              sigma_l=rng.uniform(1, 8, L), fp32=False)
+                              sigma_l=rng.uniform(1, 8, L), fp32=False, kernel_width=kernel_width)
 
 
-@pytest.mark.parametrize("W,H,L,seed", [(20, 16, 3, 1), (40, 36, 5, 2)])
-def test_adjoint_dot_product(orc, W, H, L, seed):
+@pytest.mark.parametrize("W,H,L,seed,kw", [(20, 16, 3, 1, 5), (40, 36, 5, 2, 5), (23, 17, 2, 3, 3)])
+def test_adjoint_dot_product(orc, W, H, L, seed, kw):
     nz, dz, cv, P = _vjp_case(W, H, L, seed)
+    P.kernel_width = kw
     rng = np.random.default_rng(seed + 100)
     v = rng.normal(size=W * H)
     dcv = rng.normal(size=(W * H, 2))
