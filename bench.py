@@ -309,6 +309,17 @@ def main():
     lbvh.close()
     del tri_d, obj_d
 
+    # the G-buffer by rasterisation (same texels as the ray-traced one)
+    rwork = torch.empty(B.dhr_gbuffer_raster_workspace_bytes(W, H, scene.n_tris) // 4 + 64, device=dev)
+    B.dhr_gbuffer_raster(ctx, bvh, cams[f], cams[f - 1], W, H, cur["pos"], cur["nz"], cur["dz"], cur["mv"], rwork)
+    er[4].record()
+    for _ in range(5):
+        B.dhr_gbuffer_raster(ctx, bvh, cams[f], cams[f - 1], W, H, cur["pos"], cur["nz"], cur["dz"], cur["mv"], rwork)
+    er[5].record()
+    torch.cuda.synchronize()
+    line["gbuffer_raster"] = {"ms": er[4].elapsed_time(er[5]) / 5, "ray_traced_ms": per["gbuf"]}
+    del rwork
+
     # wire form of the last frame: AO bytes + per-light bits (memory-bound)
     q8 = torch.empty(HW, dtype=torch.uint8, device=dev)
     m8 = torch.empty(HW, dtype=torch.uint8, device=dev)

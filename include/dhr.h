@@ -238,6 +238,27 @@ typedef struct {
 } dhr_gbuffer_job;
 dhr_status dhr_gbuffer_batch(dhr_ctx* ctx, const dhr_gbuffer_job* jobs, uint32_t n_jobs, dhr_stream stream);
 
+/* The same G-buffer by rasterisation (Section 2.2: the server rasterises
+ * its G-buffer and traces visibility from it).  Each triangle proposes the
+ * pixels of its conservative screen box (clipped to the camera's near side,
+ * grown by half a pixel; triangles whose plane passes within about 1e-5 of
+ * the eye coordinates' scale propose the whole frame), each candidate is
+ * decided by the ray-triangle test of the traversal, and a pixel keeps the
+ * minimum of (t, input index): the texels equal dhr_gbuffer's on the same
+ * triangles bit for bit, with any BVH from either builder (its triangle
+ * records are read, not its nodes).
+ *   work        device scratch of dhr_gbuffer_raster_workspace_bytes(W, H,
+ *               n_tris) bytes, 16-byte aligned (per-pixel keys, the list of
+ *               large triangles, their 8x8 tiles); calls that overlap need
+ *               disjoint work
+ *   work_bytes  its size
+ * Asynchronous on `stream`.  Errors: INVALID_ARG (null, misaligned or short
+ * buffer, bad size, degenerate camera, foreign BVH). */
+uint64_t dhr_gbuffer_raster_workspace_bytes(uint32_t W, uint32_t H, uint32_t n_tris);
+dhr_status dhr_gbuffer_raster(dhr_ctx* ctx, const dhr_bvh* bvh, const dhr_camera* cur, const dhr_camera* prev,
+                              uint32_t W, uint32_t H, float* pos, float* nz, float* dz, float* mv, void* work,
+                              uint64_t work_bytes, dhr_stream stream);
+
 typedef struct {
     const dhr_bvh* bvh;
     dhr_trace_params params;

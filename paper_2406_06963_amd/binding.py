@@ -105,7 +105,8 @@ EXPORTS = ["dhr_create", "dhr_destroy", "dhr_last_error", "dhr_sync", "dhr_versi
            "dhr_bvh_get_info", "dhr_bvh_destroy", "dhr_gbuffer", "dhr_trace_visibility", "dhr_gbuffer_batch",
            "dhr_trace_visibility_batch", "dhr_svgf_default_params", "dhr_svgf_filter", "dhr_svgf_spatial_forward",
            "dhr_svgf_backward", "dhr_svgf_workspace_bytes", "dhr_philox4x32_10", "dhr_set_trace_counters",
-           "dhr_encode_frame", "dhr_build_bvh_device", "dhr_refit_bvh", "dhr_bvh_export"]
+           "dhr_encode_frame", "dhr_build_bvh_device", "dhr_refit_bvh", "dhr_bvh_export",
+           "dhr_gbuffer_raster_workspace_bytes", "dhr_gbuffer_raster"]
 
 _lib = None
 
@@ -150,6 +151,10 @@ def load(path: str = LIB_PATH):
     L.dhr_build_bvh_device.argtypes = [vp, vp, vp, u32, vp, vp]
     L.dhr_refit_bvh.argtypes = [vp, vp, vp, vp]
     L.dhr_bvh_export.argtypes = [vp, vp, vp, vp, vp]
+    L.dhr_gbuffer_raster_workspace_bytes.argtypes = [u32, u32, u32]
+    L.dhr_gbuffer_raster_workspace_bytes.restype = u64
+    L.dhr_gbuffer_raster.argtypes = [vp, vp, C.POINTER(dhr_camera), C.POINTER(dhr_camera), u32, u32, vp, vp, vp, vp,
+                                     vp, u64, vp]
     _lib = L
     return L
 
@@ -304,6 +309,20 @@ def dhr_gbuffer(ctx, bvh, cur, prev, W, H, pos, nz, dz, mv, stream=None):
     st = load().dhr_gbuffer(ctx.handle, bvh.handle, C.byref(c), C.byref(p) if p is not None else None, W, H,
                             _ptr(pos), _ptr(nz), _ptr(dz), _ptr(mv), _stream(stream))
     _check(ctx, st, "dhr_gbuffer")
+
+
+def dhr_gbuffer_raster_workspace_bytes(W, H, n_tris) -> int:
+    return int(load().dhr_gbuffer_raster_workspace_bytes(W, H, n_tris))
+
+
+def dhr_gbuffer_raster(ctx, bvh, cur, prev, W, H, pos, nz, dz, mv, work, stream=None):
+    """work: a device tensor of at least dhr_gbuffer_raster_workspace_bytes bytes."""
+    c = camera(cur)
+    p = camera(prev) if prev is not None else None
+    nbytes = work.numel() * work.element_size()
+    st = load().dhr_gbuffer_raster(ctx.handle, bvh.handle, C.byref(c), C.byref(p) if p is not None else None, W, H,
+                                   _ptr(pos), _ptr(nz), _ptr(dz), _ptr(mv), _ptr(work), nbytes, _stream(stream))
+    _check(ctx, st, "dhr_gbuffer_raster")
 
 
 def dhr_trace_visibility(ctx, bvh, params, pos, nz, ao_count, shadow_count, debug_ray_bits=None, stream=None):

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdhr.so")
-SOURCES = ["api.cpp", "bvh_build.cpp", "trace.hip", "svgf.hip", "svgf_bwd.hip", "encode.hip", "bvh_device.hip"]
+SOURCES = ["api.cpp", "bvh_build.cpp", "trace.hip", "svgf.hip", "svgf_bwd.hip", "encode.hip", "bvh_device.hip", "raster.hip"]
 ARCH = "gfx950"
 
 

@@ -321,29 +321,40 @@ dhr_status dhr_build_bvh(dhr_ctx* ctx, const float* tris, const uint32_t* obj_id
     dhr_bvh* b = new dhr_bvh;
     b->ctx = ctx;
     b->device = ctx->device;
-    const size_t nb = hb.n_nodes * 4 * sizeof(float4), tb = 3ull * T * sizeof(float4);
-    if (hipMalloc(&b->nodes, nb) != hipSuccess || hipMalloc(&b->tris, tb) != hipSuccess) {
+    const size_t nb = hb.n_nodes * 4 * sizeof(float4), tb = 3ull * T * sizeof(float4), rb = 4ull * T;
+    if (hipMalloc(&b->nodes, nb) != hipSuccess || hipMalloc(&b->tris, tb) != hipSuccess ||
+        hipMalloc(&b->rec_of, rb) != hipSuccess) {
         if (b->nodes) (void)hipFree(b->nodes);
+        if (b->tris) (void)hipFree(b->tris);
         delete b;
         std::free(hb.nodes);
         std::free(hb.tris);
         (void)hipGetLastError();
-        return dhr::set_error(ctx, DHR_ERR_OOM, "dhr_build_bvh: device allocation of %zu bytes failed", nb + tb);
+        return dhr::set_error(ctx, DHR_ERR_OOM, "dhr_build_bvh: device allocation of %zu bytes failed", nb + tb + rb);
+    }
+    // inverse of the leaf order (the input index sits in v0.w of each record)
+    std::vector<uint32_t> rec_of(T);
+    for (uint32_t k = 0; k < T; ++k) {
+        uint32_t orig;
+        std::memcpy(&orig, &hb.tris[3ull * k].w, 4);
+        rec_of[orig] = k;
     }
     hipError_t e1 = hipMemcpy(b->nodes, hb.nodes, nb, hipMemcpyHostToDevice);
     hipError_t e2 = hipMemcpy(b->tris, hb.tris, tb, hipMemcpyHostToDevice);
+    if (e2 == hipSuccess) e2 = hipMemcpy(b->rec_of, rec_of.data(), rb, hipMemcpyHostToDevice);
     std::free(hb.nodes);
     std::free(hb.tris);
     if (e1 != hipSuccess || e2 != hipSuccess) {
         (void)hipFree(b->nodes);
         (void)hipFree(b->tris);
+        (void)hipFree(b->rec_of);
         delete b;
         return dhr::set_error(ctx, DHR_ERR_DEVICE, "dhr_build_bvh: upload failed: %s",
                               hipGetErrorString(e1 != hipSuccess ? e1 : e2));
     }
     b->info.n_nodes = hb.n_nodes;
     b->info.n_tris = T;
-    b->info.device_bytes = nb + tb;
+    b->info.device_bytes = nb + tb + rb;
     b->info.depth = hb.depth;
     b->info.max_leaf_size = hb.max_leaf_size;
     b->info.sah_cost = hb.sah_cost;
@@ -372,8 +383,8 @@ dhr_status dhr_bvh_get_info(const dhr_bvh* bvh, dhr_bvh_info* info) {
 void dhr_bvh_destroy(dhr_bvh* bvh) {
     if (!bvh) return;
     dhr::DeviceGuard g(bvh->device);
-    for (void* p : {(void*)bvh->nodes, (void*)bvh->tris, (void*)bvh->child, (void*)bvh->parent, (void*)bvh->box,
-                    (void*)bvh->by_depth, (void*)bvh->bounds})
+    for (void* p : {(void*)bvh->nodes, (void*)bvh->tris, (void*)bvh->rec_of, (void*)bvh->child, (void*)bvh->parent,
+                    (void*)bvh->box, (void*)bvh->by_depth, (void*)bvh->bounds})
         if (p) (void)hipFree(p);
     delete bvh;
 }

@@ -136,9 +136,10 @@ __global__ __launch_bounds__(kB) void karras_kernel(const uint32_t* __restrict__
 // ---- leaves: triangle records in sorted order and their boxes ----
 __global__ __launch_bounds__(kB) void leaves_kernel(const float* __restrict__ tris, const uint32_t* __restrict__ obj,
                                                     const uint32_t* __restrict__ order, uint32_t T, float4* tri_out,
-                                                    float* box) {
+                                                    float* box, uint32_t* rec_of) {
     const uint32_t k = blockIdx.x * kB + threadIdx.x;
     if (k >= T) return;
+    if (order) rec_of[order[k]] = k;
     // build: sorted position k holds input triangle order[k]; refit (order
     // NULL): the current record holds the input index and the object id
     const uint32_t src = order ? order[k] : __float_as_uint(tri_out[3ull * k].w);
@@ -244,11 +245,11 @@ dhr_status fill(dhr_ctx* ctx, dhr_bvh* b, const float* tris, const uint32_t* obj
     hipLaunchKernelGGL(bounds_kernel, dim3(nb), dim3(kB), 0, s, tris, T, b->bounds);
     hipLaunchKernelGGL(bounds_final_kernel, dim3(1), dim3(64), 0, s, b->bounds, nb);
     if (T == 1) {
-        hipLaunchKernelGGL(leaves_kernel, dim3(1), dim3(kB), 0, s, tris, obj, order, T, b->tris, b->box);
+        hipLaunchKernelGGL(leaves_kernel, dim3(1), dim3(kB), 0, s, tris, obj, order, T, b->tris, b->box, b->rec_of);
         hipLaunchKernelGGL(single_root_kernel, dim3(1), dim3(1), 0, s, tris, b->bounds, b->nodes);
         return check_launch(ctx, what);
     }
-    hipLaunchKernelGGL(leaves_kernel, dim3(blocks(T)), dim3(kB), 0, s, tris, obj, order, T, b->tris, b->box);
+    hipLaunchKernelGGL(leaves_kernel, dim3(blocks(T)), dim3(kB), 0, s, tris, obj, order, T, b->tris, b->box, b->rec_of);
     for (size_t l = 0; l + 1 < b->level_off.size(); ++l) {
         const uint32_t o = b->level_off[l], n = b->level_off[l + 1] - o;
         if (n) hipLaunchKernelGGL(merge_kernel, dim3(blocks(n)), dim3(kB), 0, s, b->by_depth + o, n, b->child, T, b->box);
@@ -258,8 +259,8 @@ dhr_status fill(dhr_ctx* ctx, dhr_bvh* b, const float* tris, const uint32_t* obj
 }
 
 void release(dhr_bvh* b) {
-    for (void* p : {(void*)b->nodes, (void*)b->tris, (void*)b->child, (void*)b->parent, (void*)b->box,
-                    (void*)b->by_depth, (void*)b->bounds})
+    for (void* p : {(void*)b->nodes, (void*)b->tris, (void*)b->rec_of, (void*)b->child, (void*)b->parent,
+                    (void*)b->box, (void*)b->by_depth, (void*)b->bounds})
         if (p) (void)hipFree(p);
     delete b;
 }
@@ -294,6 +295,7 @@ dhr_status dhr_build_bvh_device(dhr_ctx* ctx, const float* tris, const uint32_t*
     (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_depth, key, key2, val, order, (int)NI, 0, 6, s);
     tmp_bytes = std::max(tmp_bytes, tmp_depth);
     bool ok = hipMalloc(&b->nodes, NI * 64) == hipSuccess && hipMalloc(&b->tris, 48ull * T) == hipSuccess &&
+              hipMalloc(&b->rec_of, 4ull * T) == hipSuccess &&
               hipMalloc(&b->child, sizeof(int2) * NI) == hipSuccess &&
               hipMalloc(&b->parent, sizeof(int) * (NI + T)) == hipSuccess &&
               hipMalloc(&b->box, 24ull * (NI + T)) == hipSuccess && hipMalloc(&b->by_depth, 4ull * NI) == hipSuccess &&
@@ -364,7 +366,7 @@ dhr_status dhr_build_bvh_device(dhr_ctx* ctx, const float* tris, const uint32_t*
     const uint32_t depth = T > 1 ? (uint32_t)b->level_off.size() : 2u;
     b->info.n_nodes = NI;
     b->info.n_tris = T;
-    b->info.device_bytes = NI * 64 + 48ull * T;
+    b->info.device_bytes = NI * 64 + 52ull * T;
     b->info.depth = depth;
     b->info.max_leaf_size = 1;
     b->info.sah_cost = 0.0;

@@ -6,6 +6,13 @@
 
 #include <cstdint>
 
+// Every helper below rounds each operation on its own unless an fmaf is
+// written out: the rasterised and the ray-traced G-buffer inline the same
+// helpers into different kernels and must produce the same bits, which
+// contraction chosen per inlining context would not guarantee.  The build's
+// setting is restored at the end of the header.
+#pragma clang fp contract(off)
+
 namespace dhr {
 
 // ---------------------------------------------------------------- float3 math
@@ -14,9 +21,9 @@ __device__ __forceinline__ float3 f3(float4 v) { return make_float3(v.x, v.y, v.
 __device__ __forceinline__ float3 operator+(float3 a, float3 b) { return f3(a.x + b.x, a.y + b.y, a.z + b.z); }
 __device__ __forceinline__ float3 operator-(float3 a, float3 b) { return f3(a.x - b.x, a.y - b.y, a.z - b.z); }
 __device__ __forceinline__ float3 operator*(float3 a, float s) { return f3(a.x * s, a.y * s, a.z * s); }
-__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
 __device__ __forceinline__ float3 cross3(float3 a, float3 b) {
-    return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+    return f3(fmaf(a.y, b.z, -(a.z * b.y)), fmaf(a.z, b.x, -(a.x * b.z)), fmaf(a.x, b.y, -(a.y * b.x)));
 }
 __device__ __forceinline__ float3 normalize3(float3 a) { return a * (1.0f / sqrtf(dot3(a, a))); }
 
@@ -182,7 +189,7 @@ __device__ __forceinline__ float tri_t_rec(float4 v0, float4 e1, float4 e2, floa
     const float3 E1 = f3(e1), E2 = f3(e2);
     const float3 p = cross3(d, E2);
     const float det = dot3(E1, p);
-    const float inv = 1.0f / det;
+    const float inv = __builtin_amdgcn_rcpf(det);
     const float3 tv = o - f3(v0);
     const float u = dot3(tv, p) * inv;
     const float3 q = cross3(tv, E1);
@@ -367,3 +374,5 @@ __device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, con
 }
 
 }  // namespace dhr
+
+#pragma clang fp contract(fast)

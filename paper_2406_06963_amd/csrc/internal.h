@@ -25,6 +25,7 @@ struct dhr_bvh {
     int device = 0;
     float4* nodes = nullptr;
     float4* tris = nullptr;
+    uint32_t* rec_of = nullptr;  // [T]: leaf-order record of each input triangle
     dhr_bvh_info info{};
     // topology kept by the device build for refits (NULL for host builds):
     // children of each internal node, parents of internal nodes and leaves,

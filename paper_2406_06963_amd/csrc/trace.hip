@@ -10,6 +10,7 @@
 #include <cstring>
 #include <vector>
 
+#include "camera.h"
 #include "device.h"
 #include "internal.h"
 
@@ -17,11 +18,6 @@ namespace dhr {
 namespace {
 
 constexpr int kTileW = 16, kTileH = 8, kBlock = 128;
-
-struct CamD {
-    float eye[3], fwd[3], right[3], up[3];
-    float tx, ty;  // tan(fov/2) * aspect, tan(fov/2)
-};
 
 struct LightD {
     uint32_t kind;
@@ -64,14 +60,6 @@ __device__ __forceinline__ void tile_pixel(uint32_t t, uint32_t tiles_x, uint32_
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     x = (t % tiles_x) * kTileW + w * 8 + (lane & 7);
     y = (t / tiles_x) * kTileH + (lane >> 3);
-}
-
-__device__ __forceinline__ float3 cam_dir(const CamD& c, float px, float py, uint32_t W, uint32_t H) {
-    const float sx = (2.0f * px / (float)W - 1.0f) * c.tx;
-    const float sy = (1.0f - 2.0f * py / (float)H) * c.ty;
-    const float3 d = f3(c.fwd[0] + c.right[0] * sx + c.up[0] * sy, c.fwd[1] + c.right[1] * sx + c.up[1] * sy,
-                        c.fwd[2] + c.right[2] * sx + c.up[2] * sy);
-    return normalize3(d);
 }
 
 // Ray `sample` of stream st (0 = AO, l + 1 = light l) of pixel (x, y) with
@@ -235,54 +223,11 @@ __global__ __launch_bounds__(kBlock) void gbuffer_kernel(const GbufBatch B) {
     const size_t i = (size_t)y * D.W + x;
     const CamD& C = D.cur;
     const float3 eye = f3(C.eye[0], C.eye[1], C.eye[2]);
-    const float3 fwd = f3(C.fwd[0], C.fwd[1], C.fwd[2]);
-    const float3 d = cam_dir(C, x + 0.5f, y + 0.5f, D.W, D.H);
+    const float3 d = cam_dir(C, x + 0.5f, y + 0.5f);
     float t;
     const int hit = closest_hit(D.nodes, D.tris, eye, d, true, t, stack + (threadIdx.x >> 6) * kStack);
-    if (hit < 0) {
-        D.pos[i] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(DHR_MISS_ID));
-        D.nz[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        D.dz[i] = make_float2(0.0f, 0.0f);
-        D.mv[i] = make_float2(0.0f, 0.0f);
-        return;
-    }
-    const float4 v0 = D.tris[3 * hit + 0];
-    const float4 e1 = D.tris[3 * hit + 1];
-    const float4 e2 = D.tris[3 * hit + 2];
-    const float3 P = eye + d * t;
-    float3 nrm = normalize3(cross3(f3(e1), f3(e2)));
-    if (dot3(nrm, d) > 0.0f) nrm = nrm * -1.0f;
-    const float z = t * dot3(d, fwd);
-    D.pos[i] = make_float4(P.x, P.y, P.z, e1.w);
-    D.nz[i] = make_float4(nrm.x, nrm.y, nrm.z, z);
-    // depth of the hit plane through the pixel to the right and the one below
-    float dzv[2];
-    const float pd = dot3(f3(v0) - eye, nrm);
-    for (int k = 0; k < 2; ++k) {
-        const float3 d1 = cam_dir(C, x + 0.5f + (k == 0), y + 0.5f + (k == 1), D.W, D.H);
-        const float den = dot3(d1, nrm);
-        float out = 1e20f;
-        if (den != 0.0f) {
-            const float t1 = pd / den;
-            if (t1 > 0.0f) out = t1 * dot3(d1, fwd) - z;
-        }
-        dzv[k] = out;
-    }
-    D.dz[i] = make_float2(dzv[0], dzv[1]);
-    float2 mv = make_float2(__builtin_nanf(""), __builtin_nanf(""));
-    if (D.has_prev) {
-        const CamD& Q = D.prev;
-        const float3 v = P - f3(Q.eye[0], Q.eye[1], Q.eye[2]);
-        const float zc = dot3(v, f3(Q.fwd[0], Q.fwd[1], Q.fwd[2]));
-        if (zc > 0.0f) {
-            const float xc = dot3(v, f3(Q.right[0], Q.right[1], Q.right[2])) / zc;
-            const float yc = dot3(v, f3(Q.up[0], Q.up[1], Q.up[2])) / zc;
-            const float px = (xc / Q.tx + 1.0f) * 0.5f * (float)D.W;
-            const float py = (1.0f - yc / Q.ty) * 0.5f * (float)D.H;
-            mv = make_float2(px - (x + 0.5f), py - (y + 0.5f));
-        }
-    }
-    D.mv[i] = mv;
+    gbuffer_texel(C, D.prev, D.has_prev != 0, D.W, D.H, x, y, d, hit < 0 ? nullptr : D.tris + 3 * hit, t, D.pos[i],
+                  D.nz[i], D.dz[i], D.mv[i]);
 }
 
 __global__ void philox_kernel(uint32_t k0, uint32_t k1, const uint4* __restrict__ ctr, uint4* __restrict__ out,
@@ -292,32 +237,6 @@ __global__ void philox_kernel(uint32_t k0, uint32_t k1, const uint4* __restrict_
 }
 
 // ------------------------------------------------------------------ host side
-
-bool make_cam(const dhr_camera& c, uint32_t W, uint32_t H, CamD* out) {
-    double e[3], f[3];
-    for (int k = 0; k < 3; ++k) {
-        e[k] = c.eye[k];
-        f[k] = (double)c.target[k] - (double)c.eye[k];
-    }
-    double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
-    if (!(fl > 0.0) || !std::isfinite(fl) || !(c.fov_y > 0.0f) || !(c.fov_y < 3.14f)) return false;
-    for (double& v : f) v /= fl;
-    double r[3] = {f[1] * 0.0 - f[2] * 1.0, f[2] * 0.0 - f[0] * 0.0, f[0] * 1.0 - f[1] * 0.0};  // fwd x (0,1,0)
-    double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-    if (!(rl > 1e-9)) return false;
-    for (double& v : r) v /= rl;
-    double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
-    for (int k = 0; k < 3; ++k) {
-        out->eye[k] = (float)e[k];
-        out->fwd[k] = (float)f[k];
-        out->right[k] = (float)r[k];
-        out->up[k] = (float)u[k];
-    }
-    const double th = std::tan(0.5 * (double)c.fov_y);
-    out->tx = (float)(th * (double)W / (double)H);
-    out->ty = (float)th;
-    return true;
-}
 
 bool size_ok(uint32_t W, uint32_t H) { return W >= 1 && H >= 1 && W <= DHR_MAX_SIDE && H <= DHR_MAX_SIDE; }
 
