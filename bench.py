@@ -309,6 +309,29 @@ def main():
     lbvh.close()
     del tri_d, obj_d
 
+    # the terrain's boxes as instances of one cube (two-level hierarchy)
+    if "instances" in scene.meta:
+        bt, bo, mesh, xf, iid = wl.instanced_form(scene)
+        tb = time.perf_counter()
+        ibvh = B.dhr_build_bvh_instanced(ctx, bt, bo, mesh, xf, iid)
+        ib_s = time.perf_counter() - tb
+        ii = ibvh.info()
+        ei = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        B.dhr_gbuffer(ctx, ibvh, cams[f], cams[f - 1], W, H, cur["pos"], cur["nz"], cur["dz"], cur["mv"])
+        ei[0].record()
+        for _ in range(5):
+            B.dhr_gbuffer(ctx, ibvh, cams[f], cams[f - 1], W, H, cur["pos"], cur["nz"], cur["dz"], cur["mv"])
+        ei[1].record()
+        for _ in range(5):
+            B.dhr_trace_visibility(ctx, ibvh, tp, cur["pos"], cur["nz"], ao, sh)
+        ei[2].record()
+        torch.cuda.synchronize()
+        line["instanced"] = {"instances": int(len(xf)), "build_s": ib_s, "device_mb": ii["device_bytes"] / 2 ** 20,
+                             "flat_device_mb": info["device_bytes"] / 2 ** 20,
+                             "gbuf_ms": ei[0].elapsed_time(ei[1]) / 5, "trace_ms": ei[1].elapsed_time(ei[2]) / 5,
+                             "flat_gbuf_ms": per["gbuf"], "flat_trace_ms": per["trace"]}
+        ibvh.close()
+
     # the G-buffer by rasterisation (same texels as the ray-traced one)
     rwork = torch.empty(B.dhr_gbuffer_raster_workspace_bytes(W, H, scene.n_tris) // 4 + 64, device=dev)
     B.dhr_gbuffer_raster(ctx, bvh, cams[f], cams[f - 1], W, H, cur["pos"], cur["nz"], cur["dz"], cur["mv"], rwork)

@@ -124,6 +124,29 @@ dhr_status dhr_build_bvh(dhr_ctx* ctx, const float* tris, const uint32_t* obj_id
 dhr_status dhr_build_bvh_device(dhr_ctx* ctx, const float* tris, const uint32_t* obj_id, uint32_t T, dhr_bvh** out,
                                 dhr_stream stream);
 
+/* Two-level hierarchy for instanced geometry (the large terrain workload
+ * places thousands of copies of one box): a top level over the instances'
+ * world boxes, bottom level 0 over the base geometry, bottom level 1 over
+ * one mesh that every instance places with its own transform.  Rays enter
+ * the mesh's hierarchy transformed into its space (direction not
+ * renormalised, so t is shared), and every query answers as on the
+ * flattened scene: base triangles first (index i), then instance k's copy
+ * of mesh triangle j (index n_base + k n_mesh + j) for ties.  Host build,
+ * synchronous, like dhr_build_bvh (whose options apply to all three levels).
+ *   base_tris  host float[n_base][3][3]; base_obj host uint32[n_base] or NULL
+ *   mesh_tris  host float[n_mesh][3][3] in the mesh's own space
+ *   xforms     host float[n_inst][12]: row-major 3x4 object-to-world [A | t]
+ *              (A invertible)
+ *   inst_obj   host uint32[n_inst] object id of each instance, or NULL (then k)
+ * Accepted by dhr_gbuffer(_batch) and dhr_trace_visibility(_batch); not by
+ * dhr_gbuffer_raster, dhr_refit_bvh, dhr_bvh_export or the work counters
+ * (UNSUPPORTED).  Errors: INVALID_ARG (null pointer, a count of 0 or beyond
+ * 2^28 base / 2^20 mesh / 2^24 instances, non-finite or singular transform,
+ * the reserved object id), OOM. */
+dhr_status dhr_build_bvh_instanced(dhr_ctx* ctx, const float* base_tris, const uint32_t* base_obj, uint32_t n_base,
+                                   const float* mesh_tris, uint32_t n_mesh, const float* xforms,
+                                   const uint32_t* inst_obj, uint32_t n_inst, const dhr_bvh_opts* opts, dhr_bvh** out);
+
 /* Refit of a device-built BVH after its triangles moved: same count, same
  * order, same object ids.  Triangle records and boxes are recomputed from
  * `tris` (device float[T][3][3]) and the topology is kept, so queries stay

@@ -106,7 +106,7 @@ EXPORTS = ["dhr_create", "dhr_destroy", "dhr_last_error", "dhr_sync", "dhr_versi
            "dhr_trace_visibility_batch", "dhr_svgf_default_params", "dhr_svgf_filter", "dhr_svgf_spatial_forward",
            "dhr_svgf_backward", "dhr_svgf_workspace_bytes", "dhr_philox4x32_10", "dhr_set_trace_counters",
            "dhr_encode_frame", "dhr_build_bvh_device", "dhr_refit_bvh", "dhr_bvh_export",
-           "dhr_gbuffer_raster_workspace_bytes", "dhr_gbuffer_raster"]
+           "dhr_gbuffer_raster_workspace_bytes", "dhr_gbuffer_raster", "dhr_build_bvh_instanced"]
 
 _lib = None
 
@@ -151,6 +151,8 @@ def load(path: str = LIB_PATH):
     L.dhr_build_bvh_device.argtypes = [vp, vp, vp, u32, vp, vp]
     L.dhr_refit_bvh.argtypes = [vp, vp, vp, vp]
     L.dhr_bvh_export.argtypes = [vp, vp, vp, vp, vp]
+    L.dhr_build_bvh_instanced.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, u32, C.POINTER(dhr_bvh_opts),
+                                          C.POINTER(vp)]
     L.dhr_gbuffer_raster_workspace_bytes.argtypes = [u32, u32, u32]
     L.dhr_gbuffer_raster_workspace_bytes.restype = u64
     L.dhr_gbuffer_raster.argtypes = [vp, vp, C.POINTER(dhr_camera), C.POINTER(dhr_camera), u32, u32, vp, vp, vp, vp,
@@ -300,6 +302,25 @@ def dhr_build_bvh(ctx: Context, tris, obj_id=None, max_leaf=4, max_depth=32, sah
                               None if ids is None else ids.ctypes.data_as(C.c_void_p), t.shape[0],
                               C.byref(opts), C.byref(h))
     _check(ctx, st, "dhr_build_bvh")
+    return Bvh(ctx, h)
+
+
+def dhr_build_bvh_instanced(ctx: Context, base_tris, base_obj, mesh_tris, xforms, inst_obj=None, max_leaf=4,
+                            max_depth=32, sah_bins=16, threads=0) -> Bvh:
+    """Host arrays: base_tris [n,3,3], base_obj [n] or None, mesh_tris [m,3,3],
+    xforms [k,3,4] (object to world), inst_obj [k] or None."""
+    import numpy as np
+    bt = np.ascontiguousarray(base_tris, dtype=np.float32).reshape(-1, 9)
+    bo = None if base_obj is None else np.ascontiguousarray(base_obj, dtype=np.uint32)
+    mt = np.ascontiguousarray(mesh_tris, dtype=np.float32).reshape(-1, 9)
+    xf = np.ascontiguousarray(xforms, dtype=np.float32).reshape(-1, 12)
+    io = None if inst_obj is None else np.ascontiguousarray(inst_obj, dtype=np.uint32)
+    opts = dhr_bvh_opts(max_leaf, max_depth, sah_bins, threads)
+    h = C.c_void_p()
+    p = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
+    st = load().dhr_build_bvh_instanced(ctx.handle, p(bt), p(bo), bt.shape[0], p(mt), mt.shape[0], p(xf), p(io),
+                                        xf.shape[0], C.byref(opts), C.byref(h))
+    _check(ctx, st, "dhr_build_bvh_instanced")
     return Bvh(ctx, h)
 
 

@@ -363,9 +363,190 @@ dhr_status dhr_build_bvh(dhr_ctx* ctx, const float* tris, const uint32_t* obj_id
     return DHR_OK;
 }
 
+dhr_status dhr_build_bvh_instanced(dhr_ctx* ctx, const float* base_tris, const uint32_t* base_obj, uint32_t n_base,
+                                   const float* mesh_tris, uint32_t n_mesh, const float* xforms,
+                                   const uint32_t* inst_obj, uint32_t n_inst, const dhr_bvh_opts* opts, dhr_bvh** out) {
+    using namespace dhr;
+    if (!ctx) return DHR_ERR_INVALID_ARG;
+    const char* what = "dhr_build_bvh_instanced";
+    if (!base_tris || !mesh_tris || !xforms || !out) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: null pointer", what);
+    *out = nullptr;
+    if (n_base == 0 || n_mesh == 0 || n_inst == 0 || n_base > (1u << 28) || n_mesh > (1u << 20) ||
+        n_inst > (1u << 24) || (uint64_t)n_base + (uint64_t)n_inst * n_mesh > 0x7FFFFFFFull)
+        return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: counts outside the supported range", what);
+    dhr_bvh_opts o{4, 32, 16, 0};
+    if (opts) o = *opts;
+    if (o.max_leaf == 0) o.max_leaf = 4;
+    if (o.max_depth == 0) o.max_depth = 32;
+    if (o.sah_bins == 0) o.sah_bins = 16;
+    if (o.max_leaf > 8 || o.max_depth < 8 || o.max_depth > 32 || o.sah_bins < 4 || o.sah_bins > 64)
+        return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: options out of range", what);
+    for (uint32_t n : {n_base, n_inst + 1})
+        if ((uint64_t)(n + o.max_leaf - 1) / o.max_leaf > (1ull << o.max_depth))
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: max_depth too small", what);
+    if (base_obj)
+        for (uint32_t i = 0; i < n_base; ++i)
+            if (base_obj[i] == DHR_MISS_ID)
+                return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: object id 0xFFFFFFFF is reserved", what);
+    if (inst_obj)
+        for (uint32_t k = 0; k < n_inst; ++k)
+            if (inst_obj[k] == DHR_MISS_ID)
+                return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: object id 0xFFFFFFFF is reserved", what);
+    const auto t0 = std::chrono::steady_clock::now();
+    // instance transforms: object-to-world M = [A | t], world-to-object [A^-1 | -A^-1 t] (double)
+    std::vector<double> inv(12ull * n_inst);
+    for (uint32_t k = 0; k < n_inst; ++k) {
+        const float* m = xforms + 12ull * k;
+        for (int q = 0; q < 12; ++q)
+            if (!std::isfinite(m[q])) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: transform %u not finite", what, k);
+        const double a = m[0], b = m[1], c = m[2], d = m[4], e = m[5], f = m[6], g = m[8], h = m[9], i = m[10];
+        const double det = a * (e * i - f * h) - b * (d * i - f * g) + c * (d * h - e * g);
+        const double scale = std::max({std::fabs(a), std::fabs(b), std::fabs(c), std::fabs(d), std::fabs(e),
+                                       std::fabs(f), std::fabs(g), std::fabs(h), std::fabs(i)});
+        if (!(std::fabs(det) > 1e-12 * scale * scale * scale))
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: transform %u is singular", what, k);
+        const double r[9] = {(e * i - f * h) / det, (c * h - b * i) / det, (b * f - c * e) / det,
+                             (f * g - d * i) / det, (a * i - c * g) / det, (c * d - a * f) / det,
+                             (d * h - e * g) / det, (b * g - a * h) / det, (a * e - b * d) / det};
+        double* w = inv.data() + 12ull * k;
+        for (int row = 0; row < 3; ++row) {
+            for (int col = 0; col < 3; ++col) w[4 * row + col] = r[3 * row + col];
+            w[4 * row + 3] = -(r[3 * row] * m[3] + r[3 * row + 1] * m[7] + r[3 * row + 2] * m[11]);
+        }
+    }
+    HostBvh hb[3];  // base, mesh, top
+    if (!build_host_bvh(base_tris, base_obj, n_base, o, &hb[0]))
+        return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: base geometry: %s", what, hb[0].error.c_str());
+    auto free_host = [&] {
+        for (HostBvh& h : hb) {
+            std::free(h.nodes);
+            std::free(h.tris);
+            h.nodes = h.tris = nullptr;
+        }
+    };
+    if (!build_host_bvh(mesh_tris, nullptr, n_mesh, o, &hb[1])) {
+        free_host();
+        return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: mesh: %s", what, hb[1].error.c_str());
+    }
+    // world boxes of the items (0: base geometry, 1 + k: instance k) as
+    // degenerate triangles (lo, hi, lo) spanning them, rounded outward
+    const uint32_t n_items = n_inst + 1;
+    std::vector<float> boxes(9ull * n_items);
+    auto put_box = [&](uint32_t item, const double* lo, const double* hi) {
+        float* bx = boxes.data() + 9ull * item;
+        for (int q = 0; q < 3; ++q) {
+            float l = (float)lo[q], h = (float)hi[q];
+            if ((double)l > lo[q]) l = std::nextafter(l, -INFINITY);
+            if ((double)h < hi[q]) h = std::nextafter(h, INFINITY);
+            bx[q] = l;
+            bx[3 + q] = h;
+            bx[6 + q] = l;
+        }
+    };
+    {
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (uint64_t v = 0; v < 3ull * n_base; ++v)
+            for (int q = 0; q < 3; ++q) {
+                lo[q] = std::min(lo[q], (double)base_tris[3 * v + q]);
+                hi[q] = std::max(hi[q], (double)base_tris[3 * v + q]);
+            }
+        put_box(0, lo, hi);
+    }
+    for (uint32_t k = 0; k < n_inst; ++k) {
+        const float* m = xforms + 12ull * k;
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (uint64_t v = 0; v < 3ull * n_mesh; ++v) {
+            const float* p = mesh_tris + 3 * v;
+            for (int q = 0; q < 3; ++q) {
+                const double w = (double)m[4 * q] * p[0] + (double)m[4 * q + 1] * p[1] + (double)m[4 * q + 2] * p[2] +
+                                 (double)m[4 * q + 3];
+                lo[q] = std::min(lo[q], w);
+                hi[q] = std::max(hi[q], w);
+            }
+        }
+        put_box(1 + k, lo, hi);
+    }
+    if (!build_host_bvh(boxes.data(), nullptr, n_items, o, &hb[2])) {
+        free_host();
+        return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: top level: %s", what, hb[2].error.c_str());
+    }
+    // instance records in the top level's leaf order
+    std::vector<float4> rec(8ull * n_items);
+    for (uint32_t pos = 0; pos < n_items; ++pos) {
+        uint32_t item;
+        std::memcpy(&item, &hb[2].tris[3ull * pos].w, 4);
+        float4* R = rec.data() + 8ull * pos;
+        double wi[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0}, fw[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
+        uint32_t info[4] = {0u, DHR_MISS_ID, 0u, 0u};
+        if (item > 0) {
+            const uint32_t k = item - 1;
+            for (int q = 0; q < 12; ++q) {
+                wi[q] = inv[12ull * k + q];
+                fw[q] = xforms[12ull * k + q];
+            }
+            info[0] = 1u;
+            info[1] = inst_obj ? inst_obj[k] : k;
+            info[2] = n_base + k * n_mesh;
+        }
+        for (int row = 0; row < 3; ++row) {
+            R[row] = make_float4((float)wi[4 * row], (float)wi[4 * row + 1], (float)wi[4 * row + 2], (float)wi[4 * row + 3]);
+            R[3 + row] = make_float4((float)fw[4 * row], (float)fw[4 * row + 1], (float)fw[4 * row + 2],
+                                     (float)fw[4 * row + 3]);
+        }
+        float fi[4];
+        std::memcpy(fi, info, 16);
+        R[6] = make_float4(fi[0], fi[1], fi[2], fi[3]);
+        R[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    // device: nodes [top | base | mesh], triangles [base | mesh], instances, description
+    DeviceGuard g(ctx->device);
+    const uint64_t nn[3] = {hb[2].n_nodes, hb[0].n_nodes, hb[1].n_nodes};
+    const uint64_t node_bytes = 64ull * (nn[0] + nn[1] + nn[2]), tri_bytes = 48ull * (n_base + n_mesh),
+                   inst_bytes = 128ull * n_items;
+    dhr_bvh* b = new dhr_bvh;
+    b->ctx = ctx;
+    b->device = ctx->device;
+    bool ok = hipMalloc(&b->nodes, node_bytes) == hipSuccess && hipMalloc(&b->tris, tri_bytes) == hipSuccess &&
+              hipMalloc(&b->inst, inst_bytes) == hipSuccess && hipMalloc(&b->tl, sizeof(TwoLevelHost)) == hipSuccess;
+    if (ok) {
+        TwoLevelHost tl;
+        tl.inst = b->inst;
+        tl.nodes[0] = b->nodes + 4 * nn[0];
+        tl.nodes[1] = b->nodes + 4 * (nn[0] + nn[1]);
+        tl.tris[0] = b->tris;
+        tl.tris[1] = b->tris + 3ull * n_base;
+        ok = hipMemcpy(b->nodes, hb[2].nodes, 64ull * nn[0], hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(b->nodes + 4 * nn[0], hb[0].nodes, 64ull * nn[1], hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(b->nodes + 4 * (nn[0] + nn[1]), hb[1].nodes, 64ull * nn[2], hipMemcpyHostToDevice) ==
+                 hipSuccess &&
+             hipMemcpy(b->tris, hb[0].tris, 48ull * n_base, hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(b->tris + 3ull * n_base, hb[1].tris, 48ull * n_mesh, hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(b->inst, rec.data(), inst_bytes, hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(b->tl, &tl, sizeof tl, hipMemcpyHostToDevice) == hipSuccess;
+    }
+    const uint32_t depth = hb[2].depth + std::max(hb[0].depth, hb[1].depth);
+    const uint32_t max_leaf = std::max({hb[0].max_leaf_size, hb[1].max_leaf_size, hb[2].max_leaf_size});
+    free_host();
+    if (!ok) {
+        (void)hipGetLastError();
+        dhr_bvh_destroy(b);
+        return set_error(ctx, DHR_ERR_OOM, "%s: device allocation or upload failed", what);
+    }
+    b->info.n_nodes = nn[0] + nn[1] + nn[2];
+    b->info.n_tris = n_base + n_mesh;
+    b->info.device_bytes = node_bytes + tri_bytes + inst_bytes;
+    b->info.depth = depth;
+    b->info.max_leaf_size = max_leaf;
+    b->info.sah_cost = 0.0;
+    b->info.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = b;
+    return DHR_OK;
+}
+
 dhr_status dhr_bvh_export(dhr_ctx* ctx, const dhr_bvh* bvh, float* nodes, float* tris, dhr_stream stream) {
     if (!ctx) return DHR_ERR_INVALID_ARG;
     if (!bvh || !nodes || !tris) return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_bvh_export: null pointer");
+    if (bvh->tl) return dhr::set_error(ctx, DHR_ERR_UNSUPPORTED, "dhr_bvh_export: a two-level hierarchy");
     dhr::DeviceGuard g(bvh->device);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (hipMemcpyAsync(nodes, bvh->nodes, bvh->info.n_nodes * 64, hipMemcpyDeviceToDevice, s) != hipSuccess ||
@@ -384,7 +565,7 @@ void dhr_bvh_destroy(dhr_bvh* bvh) {
     if (!bvh) return;
     dhr::DeviceGuard g(bvh->device);
     for (void* p : {(void*)bvh->nodes, (void*)bvh->tris, (void*)bvh->rec_of, (void*)bvh->child, (void*)bvh->parent,
-                    (void*)bvh->box, (void*)bvh->by_depth, (void*)bvh->bounds})
+                    (void*)bvh->box, (void*)bvh->by_depth, (void*)bvh->bounds, bvh->tl, (void*)bvh->inst})
         if (p) (void)hipFree(p);
     delete bvh;
 }

@@ -373,6 +373,126 @@ __device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, con
     return best;
 }
 
+// ---------------------------------------------------------------- two levels
+// A top-level hierarchy over instances: its leaves index instance records of
+// kInstStride float4 (world-to-object rows 0-2, object-to-world rows 3-5,
+// (bottom level as bits, object id override bits (0xFFFFFFFF: keep the
+// triangle's), first global triangle index as bits, 0), padding).  Bottom
+// level 0 holds the base geometry, 1 the shared mesh.  Rays enter a bottom
+// level transformed, direction not renormalised, so t is the same in both
+// spaces.  The global index of a mesh triangle (ties of the closest hit) is
+// the instance's first index plus its index in the mesh, as in the
+// flattened scene.
+struct TwoLevel {
+    const float4* inst;
+    const float4* nodes[2];
+    const float4* tris[2];
+};
+constexpr int kInstStride = 8;
+// (selects rather than indexes, so the description stays in registers)
+__device__ __forceinline__ const float4* bottom_nodes(const TwoLevel& L, int b) { return b ? L.nodes[1] : L.nodes[0]; }
+__device__ __forceinline__ const float4* bottom_tris(const TwoLevel& L, int b) { return b ? L.tris[1] : L.tris[0]; }
+
+__device__ __forceinline__ float3 xf_point(float4 r0, float4 r1, float4 r2, float3 p) {
+    return f3(fmaf(r0.x, p.x, fmaf(r0.y, p.y, fmaf(r0.z, p.z, r0.w))),
+              fmaf(r1.x, p.x, fmaf(r1.y, p.y, fmaf(r1.z, p.z, r1.w))),
+              fmaf(r2.x, p.x, fmaf(r2.y, p.y, fmaf(r2.z, p.z, r2.w))));
+}
+__device__ __forceinline__ float3 xf_dir(float4 r0, float4 r1, float4 r2, float3 v) {
+    return f3(fmaf(r0.x, v.x, fmaf(r0.y, v.y, r0.z * v.z)), fmaf(r1.x, v.x, fmaf(r1.y, v.y, r1.z * v.z)),
+              fmaf(r2.x, v.x, fmaf(r2.y, v.y, r2.z * v.z)));
+}
+
+// Walks bottom level b for the ray (o, d) in its space; `leaf(first, count)`
+// as in packet_walk.  The live lanes are those with tmax >= 0.
+template <class Leaf, class Done>
+__device__ __forceinline__ void walk_bottom(const float4* __restrict__ nodes, float3 o, float3 d, const float& tmax,
+                                            int* wstk, Leaf leaf, Done done) {
+    const float3 id = safe_inv(d);
+    const float3 ood = f3(o.x * id.x, o.y * id.y, o.z * id.z);
+    const bool live = tmax >= 0.0f;
+    if (same_octant(id, live))
+        packet_walk<false, true>(nodes, id, ood, tmax, live, wstk, leaf, done, nullptr);
+    else
+        packet_walk<false, false>(nodes, id, ood, tmax, live, wstk, leaf, done, nullptr);
+}
+
+// any_hit through a two-level hierarchy (`top` its top-level nodes); wstk2
+// is the wave's stack for the bottom levels.
+__device__ __forceinline__ bool any_hit_2l(const float4* __restrict__ top, const TwoLevel& L, const Ray& r, bool live,
+                                           int* wstk, int* wstk2) {
+    if (!__any(live)) return false;
+    const float3 id = safe_inv(r.d);
+    const float3 ood = f3(r.o.x * id.x, r.o.y * id.y, r.o.z * id.z);
+    float tmax = live ? r.tmax : -1.0f;
+    bool hit = false;
+    auto done = [&] { return !__any(tmax >= 0.0f); };
+    auto top_leaf = [&](int first, int count) {
+        for (int k = 0; k < count && !done(); ++k) {
+            const float4* I = L.inst + kInstStride * (first + k);
+            const float4 m0 = ld_const(I, 0), m1 = ld_const(I, 1), m2 = ld_const(I, 2);
+            const int b = (int)fbits(ld_const(I, 6).x);
+            const float3 o = xf_point(m0, m1, m2, r.o), d = xf_dir(m0, m1, m2, r.d);
+            const float4* tb = bottom_tris(L, b);
+            auto leaf = [&](int f, int c) {
+                for (int j = 0; j < c; ++j)
+                    if (tri_hits_uniform(tb, f + j, o, d, tmax)) {  // false for finished lanes
+                        hit = true;
+                        tmax = -1.0f;
+                    }
+            };
+            walk_bottom(bottom_nodes(L, b), o, d, tmax, wstk2, leaf, done);
+        }
+    };
+    if (same_octant(id, live))
+        packet_walk<false, true>(top, id, ood, tmax, live, wstk, top_leaf, done, nullptr);
+    else
+        packet_walk<false, false>(top, id, ood, tmax, live, wstk, top_leaf, done, nullptr);
+    return hit;
+}
+
+// closest_hit through a two-level hierarchy: the instance and the triangle
+// (position in its bottom level's leaf order) of the hit, or inst = -1.
+__device__ __forceinline__ void closest_hit_2l(const float4* __restrict__ top, const TwoLevel& L, float3 o, float3 d,
+                                               bool live, float& tbest, int& inst, int& tri, int* wstk, int* wstk2) {
+    const float3 id = safe_inv(d);
+    const float3 ood = f3(o.x * id.x, o.y * id.y, o.z * id.z);
+    inst = -1;
+    tri = -1;
+    uint32_t best_glob = 0xFFFFFFFFu;
+    tbest = live ? __builtin_inff() : -1.0f;
+    auto done = [] { return false; };
+    auto top_leaf = [&](int first, int count) {
+        for (int k = 0; k < count; ++k) {
+            const float4* I = L.inst + kInstStride * (first + k);
+            const float4 m0 = ld_const(I, 0), m1 = ld_const(I, 1), m2 = ld_const(I, 2), info = ld_const(I, 6);
+            const int b = (int)fbits(info.x);
+            const uint32_t g0 = fbits(info.z);
+            const float3 oo = xf_point(m0, m1, m2, o), dd = xf_dir(m0, m1, m2, d);
+            const float4* tb = bottom_tris(L, b);
+            auto leaf = [&](int f, int c) {
+                for (int j = 0; j < c; ++j) {
+                    uint32_t orig;
+                    const float t = tri_t_uniform(tb, f + j, oo, dd, &orig);
+                    const uint32_t g = g0 + orig;
+                    if (t > 0.0f && t <= tbest && (t < tbest || g < best_glob)) {
+                        tbest = t;
+                        inst = first + k;
+                        tri = f + j;
+                        best_glob = g;
+                    }
+                }
+            };
+            walk_bottom(bottom_nodes(L, b), oo, dd, tbest, wstk2, leaf, done);
+        }
+    };
+    if (same_octant(id, live))
+        packet_walk<false, true>(top, id, ood, tbest, live, wstk, top_leaf, done, nullptr);
+    else
+        packet_walk<false, false>(top, id, ood, tbest, live, wstk, top_leaf, done, nullptr);
+    if (!live) tbest = __builtin_inff();
+}
+
 }  // namespace dhr
 
 #pragma clang fp contract(fast)

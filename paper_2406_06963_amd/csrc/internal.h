@@ -26,6 +26,10 @@ struct dhr_bvh {
     float4* nodes = nullptr;
     float4* tris = nullptr;
     uint32_t* rec_of = nullptr;  // [T]: leaf-order record of each input triangle
+    // two-level hierarchies (dhr_build_bvh_instanced): `nodes` starts with the
+    // top level; `tl` is the device description of instances and bottom levels
+    void* tl = nullptr;
+    float4* inst = nullptr;
     dhr_bvh_info info{};
     // topology kept by the device build for refits (NULL for host builds):
     // children of each internal node, parents of internal nodes and leaves,
@@ -67,6 +71,15 @@ class DeviceGuard {
 
 // Checks the launch(es) just enqueued.
 dhr_status check_launch(dhr_ctx* ctx, const char* what);
+
+// Host image of the device description of a two-level hierarchy (the
+// layout of the kernels' TwoLevel: instance records, then the node and
+// triangle arrays of bottom levels 0 and 1).
+struct TwoLevelHost {
+    const float4* inst;
+    const float4* nodes[2];
+    const float4* tris[2];
+};
 
 // Host-side BVH build into flat arrays ready for upload.
 struct HostBvh {

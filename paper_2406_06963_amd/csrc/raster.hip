@@ -337,7 +337,9 @@ dhr_status dhr_gbuffer_raster(dhr_ctx* ctx, const dhr_bvh* bvh, const dhr_camera
     using namespace dhr;
     if (!ctx) return DHR_ERR_INVALID_ARG;
     const char* what = "dhr_gbuffer_raster";
-    if (!bvh || bvh->ctx != ctx || !bvh->rec_of) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: bad bvh", what);
+    if (!bvh || bvh->ctx != ctx) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: bad bvh", what);
+    if (bvh->tl || !bvh->rec_of)
+        return set_error(ctx, DHR_ERR_UNSUPPORTED, "%s: two-level hierarchies are traced, not rasterised", what);
     if (!cur) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: camera is NULL", what);
     if (W < 1 || H < 1 || W > DHR_MAX_SIDE || H > DHR_MAX_SIDE)
         return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: image %ux%u outside 1..16384", what, W, H);

@@ -29,6 +29,7 @@ struct LightD {
 struct TraceDesc {
     const float4* nodes;
     const float4* tris;
+    const TwoLevel* tl;  // two-level hierarchies: instances and bottom levels (device)
     const float4* pos;
     const float4* nz;
     uint8_t* ao;
@@ -38,6 +39,8 @@ struct TraceDesc {
     float ao_r, eps_abs;
     LightD lights[DHR_MAX_LIGHTS];
 };
+static_assert(sizeof(TwoLevel) == sizeof(TwoLevelHost) && alignof(TwoLevel) == alignof(TwoLevelHost),
+              "the host image of the two-level description must match the kernels'");
 constexpr int kTraceMaxB = 12;
 using TraceBatch = Batch<TraceDesc, kTraceMaxB>;
 static_assert(sizeof(TraceBatch) <= 4000, "kernel arguments too large");
@@ -45,6 +48,7 @@ static_assert(sizeof(TraceBatch) <= 4000, "kernel arguments too large");
 struct GbufDesc {
     const float4* nodes;
     const float4* tris;
+    const TwoLevel* tl;
     float4* pos;
     float4* nz;
     float2* dz;
@@ -117,9 +121,9 @@ __device__ __forceinline__ uint32_t pack_of(uint32_t nr) {
 
 // COUNT: the instrumented variant that also tallies rays, node visits, leaf
 // visits and triangle tests into `counters` (device uint64[4]).
-template <bool COUNT>
+template <bool COUNT, bool TWO_LEVEL>
 __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsigned long long* counters) {
-    __shared__ int stack[kStack * (kBlock / 64)];
+    __shared__ int stack[kStack * (kBlock / 64) * (TWO_LEVEL ? 2 : 1)];
     __shared__ float4 s_o[kBlock];   // the tile's ray origins, w = 1 for a valid pixel
     __shared__ float4 s_n[kBlock];   // and normals
     __shared__ uint32_t s_cnt[kBlock];
@@ -148,6 +152,9 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsig
     uint32_t n_rays = 0;
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int* wstk = stack + w * kStack;
+    int* wstk2 = stack + (TWO_LEVEL ? (kBlock / 64 + w) * kStack : 0);
+    TwoLevel L{};
+    if (TWO_LEVEL) L = *D.tl;
 
     for (uint32_t st = 0; st <= D.n_lights; ++st) {
         const uint32_t nr = st == 0 ? D.n_ao : D.n_shadow;
@@ -177,7 +184,8 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsig
             Ray r;
             bool decided, occ;
             make_ray(D, st, s, px, py, f3(so), f3(sn), v, r, decided, occ);
-            const bool h = any_hit<COUNT>(D.nodes, D.tris, r, !decided, wstk, &tc);
+            const bool h = TWO_LEVEL ? any_hit_2l(D.nodes, L, r, !decided, wstk, wstk2)
+                                     : any_hit<COUNT>(D.nodes, D.tris, r, !decided, wstk, &tc);
             if (!decided) occ = h;
             if (COUNT && !decided) ++n_rays;
             if (!v || !occ) {
@@ -213,8 +221,9 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsig
     }
 }
 
+template <bool TWO_LEVEL>
 __global__ __launch_bounds__(kBlock) void gbuffer_kernel(const GbufBatch B) {
-    __shared__ int stack[kStack * (kBlock / 64)];
+    __shared__ int stack[kStack * (kBlock / 64) * (TWO_LEVEL ? 2 : 1)];
     const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
     const GbufDesc& D = B.d[j];
     uint32_t x, y;
@@ -225,9 +234,31 @@ __global__ __launch_bounds__(kBlock) void gbuffer_kernel(const GbufBatch B) {
     const float3 eye = f3(C.eye[0], C.eye[1], C.eye[2]);
     const float3 d = cam_dir(C, x + 0.5f, y + 0.5f);
     float t;
-    const int hit = closest_hit(D.nodes, D.tris, eye, d, true, t, stack + (threadIdx.x >> 6) * kStack);
-    gbuffer_texel(C, D.prev, D.has_prev != 0, D.W, D.H, x, y, d, hit < 0 ? nullptr : D.tris + 3 * hit, t, D.pos[i],
-                  D.nz[i], D.dz[i], D.mv[i]);
+    int* wstk = stack + (threadIdx.x >> 6) * kStack;
+    if (!TWO_LEVEL) {
+        const int hit = closest_hit(D.nodes, D.tris, eye, d, true, t, wstk);
+        gbuffer_texel(C, D.prev, D.has_prev != 0, D.W, D.H, x, y, d, hit < 0 ? nullptr : D.tris + 3 * hit, t,
+                      D.pos[i], D.nz[i], D.dz[i], D.mv[i]);
+        return;
+    }
+    const TwoLevel L = *D.tl;
+    int inst, tri;
+    closest_hit_2l(D.nodes, L, eye, d, true, t, inst, tri, wstk, wstk + (kBlock / 64) * kStack);
+    float4 rec[3];
+    if (inst >= 0) {
+        // the hit triangle in world space, with the instance's object id
+        const float4* I = L.inst + kInstStride * inst;
+        const float4 f0 = I[3], f1 = I[4], f2 = I[5], info = I[6];
+        const float4* tr = bottom_tris(L, (int)fbits(info.x)) + 3 * tri;
+        const float4 v0 = tr[0], e1 = tr[1], e2 = tr[2];
+        const float3 w0 = xf_point(f0, f1, f2, f3(v0)), w1 = xf_dir(f0, f1, f2, f3(e1)), w2 = xf_dir(f0, f1, f2, f3(e2));
+        const float oid = fbits(info.y) == 0xFFFFFFFFu ? e1.w : info.y;
+        rec[0] = make_float4(w0.x, w0.y, w0.z, v0.w);
+        rec[1] = make_float4(w1.x, w1.y, w1.z, oid);
+        rec[2] = make_float4(w2.x, w2.y, w2.z, 0.0f);
+    }
+    gbuffer_texel(C, D.prev, D.has_prev != 0, D.W, D.H, x, y, d, inst < 0 ? nullptr : rec, t, D.pos[i], D.nz[i],
+                  D.dz[i], D.mv[i]);
 }
 
 __global__ void philox_kernel(uint32_t k0, uint32_t k1, const uint4* __restrict__ ctr, uint4* __restrict__ out,
@@ -273,6 +304,7 @@ void fill_trace_desc(const dhr_bvh* bvh, const dhr_trace_params& p, const float*
     std::memset(d, 0, sizeof *d);
     d->nodes = bvh->nodes;
     d->tris = bvh->tris;
+    d->tl = reinterpret_cast<const TwoLevel*>(bvh->tl);
     d->pos = reinterpret_cast<const float4*>(pos);
     d->nz = reinterpret_cast<const float4*>(nz);
     d->ao = ao;
@@ -351,11 +383,23 @@ dhr_status trace_jobs(dhr_ctx* ctx, const dhr_trace_job* jobs, uint32_t n, const
     }
     DeviceGuard g(ctx->device);
     unsigned long long* cnt = reinterpret_cast<unsigned long long*>(ctx->trace_counters);
-    if (cnt)
-        return launch_batches<TraceDesc, kTraceMaxB>(ctx, descs, tiles, trace_kernel<true>, kBlock,
-                                                     reinterpret_cast<hipStream_t>(stream), what, cnt);
-    return launch_batches<TraceDesc, kTraceMaxB>(ctx, descs, tiles, trace_kernel<false>, kBlock,
-                                                 reinterpret_cast<hipStream_t>(stream), what, cnt);
+    // one launch sequence per hierarchy kind
+    std::vector<TraceDesc> d1, d2;
+    std::vector<uint32_t> t1, t2;
+    for (uint32_t k = 0; k < n; ++k) {
+        (descs[k].tl ? d2 : d1).push_back(descs[k]);
+        (descs[k].tl ? t2 : t1).push_back(tiles[k]);
+    }
+    if (cnt && !d2.empty())
+        return set_error(ctx, DHR_ERR_UNSUPPORTED, "%s: work counters cover single-level hierarchies only", what);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    dhr_status st = DHR_OK;
+    if (!d1.empty())
+        st = cnt ? launch_batches<TraceDesc, kTraceMaxB>(ctx, d1, t1, trace_kernel<true, false>, kBlock, s, what, cnt)
+                 : launch_batches<TraceDesc, kTraceMaxB>(ctx, d1, t1, trace_kernel<false, false>, kBlock, s, what, cnt);
+    if (st == DHR_OK && !d2.empty())
+        st = launch_batches<TraceDesc, kTraceMaxB>(ctx, d2, t2, trace_kernel<false, true>, kBlock, s, what, cnt);
+    return st;
 }
 
 dhr_status gbuffer_jobs(dhr_ctx* ctx, const dhr_gbuffer_job* jobs, uint32_t n, dhr_stream stream, const char* what) {
@@ -374,6 +418,7 @@ dhr_status gbuffer_jobs(dhr_ctx* ctx, const dhr_gbuffer_job* jobs, uint32_t n, d
             return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: degenerate camera", what, k);
         d.nodes = J.bvh->nodes;
         d.tris = J.bvh->tris;
+        d.tl = reinterpret_cast<const TwoLevel*>(J.bvh->tl);
         d.pos = reinterpret_cast<float4*>(J.pos);
         d.nz = reinterpret_cast<float4*>(J.nz);
         d.dz = reinterpret_cast<float2*>(J.dz);
@@ -385,8 +430,18 @@ dhr_status gbuffer_jobs(dhr_ctx* ctx, const dhr_gbuffer_job* jobs, uint32_t n, d
         tiles[k] = tiles_of(J.W, J.H);
     }
     DeviceGuard g(ctx->device);
-    return launch_batches<GbufDesc, kGbufMaxB>(ctx, descs, tiles, gbuffer_kernel, kBlock,
-                                               reinterpret_cast<hipStream_t>(stream), what);
+    std::vector<GbufDesc> d1, d2;
+    std::vector<uint32_t> t1, t2;
+    for (uint32_t k = 0; k < n; ++k) {
+        (descs[k].tl ? d2 : d1).push_back(descs[k]);
+        (descs[k].tl ? t2 : t1).push_back(tiles[k]);
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    dhr_status st = DHR_OK;
+    if (!d1.empty()) st = launch_batches<GbufDesc, kGbufMaxB>(ctx, d1, t1, gbuffer_kernel<false>, kBlock, s, what);
+    if (st == DHR_OK && !d2.empty())
+        st = launch_batches<GbufDesc, kGbufMaxB>(ctx, d2, t2, gbuffer_kernel<true>, kBlock, s, what);
+    return st;
 }
 
 }  // namespace

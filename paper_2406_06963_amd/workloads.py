@@ -287,7 +287,28 @@ def _scene_terrain(seed=3, cells=1024, extent=256.0, amplitude=40.0, n_boxes=500
     ids = np.concatenate([np.zeros(terrain.shape[0], np.uint32),
                           np.repeat(np.arange(1, n_boxes + 1, dtype=np.uint32), 12)])
     scene.tris, scene.obj_id = tris, ids
+    # the same boxes as instances of one unit cube: object-to-world [A | t]
+    # with A = R_yaw diag(s), t = the box centre (the flattened boxes above
+    # are exactly these transforms applied to the cube's corners)
+    cs, sn = np.cos(yaw), np.sin(yaw)
+    xf = np.zeros((n_boxes, 3, 4))
+    xf[:, 0, 0], xf[:, 0, 2], xf[:, 2, 0], xf[:, 2, 2] = cs * sc, sn * sc, -sn * sc, cs * sc
+    xf[:, 1, 1] = sc
+    xf[:, 0, 3], xf[:, 2, 3] = bx, bz
+    xf[:, 1, 3] = [terrain_height(scene, bx[k], bz[k]) + 0.45 * sc[k] for k in range(n_boxes)]
+    scene.meta["instances"] = {"n_base": int(terrain.shape[0]),
+                               "mesh": np.asarray(_box((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), 0.0), np.float32),
+                               "xforms": xf.astype(np.float32),
+                               "ids": np.arange(1, n_boxes + 1, dtype=np.uint32)}
     return scene
+
+
+def instanced_form(scene: Scene):
+    """(base_tris, base_obj, mesh_tris, xforms, inst_ids) of a scene built with
+    instances (the terrain): the flattened scene is base + each instance's mesh."""
+    inst = scene.meta["instances"]
+    nb = inst["n_base"]
+    return scene.tris[:nb], scene.obj_id[:nb], inst["mesh"], inst["xforms"], inst["ids"]
 
 
 # ----------------------------------------------------------------------------
