@@ -108,8 +108,10 @@ typedef struct {
 dhr_status dhr_build_bvh(dhr_ctx* ctx, const float* tris, const uint32_t* obj_id, uint32_t T,
                          const dhr_bvh_opts* opts, dhr_bvh** out);
 /* Builds the BVH on the device from device-resident triangles: a linear BVH
- * over the Morton codes of the triangle centroids (Karras, HPG 2012), one
- * triangle per leaf, in the node layout dhr_build_bvh produces, so every call
+ * over the Morton codes of the triangle centroids (Karras, HPG 2012) whose
+ * subtrees of at most four triangles become leaves, in the node layout
+ * dhr_build_bvh produces (info.depth counts the levels before that
+ * collapse, an upper bound), so every call
  * taking a dhr_bvh accepts it and every query gives the same result as with
  * any other valid hierarchy over the same triangles.  Its tree is of lower
  * quality than the SAH build (traversal is slower) but it builds in

@@ -564,7 +564,8 @@ dhr_status dhr_bvh_get_info(const dhr_bvh* bvh, dhr_bvh_info* info) {
 void dhr_bvh_destroy(dhr_bvh* bvh) {
     if (!bvh) return;
     dhr::DeviceGuard g(bvh->device);
-    for (void* p : {(void*)bvh->nodes, (void*)bvh->tris, (void*)bvh->rec_of, (void*)bvh->child, (void*)bvh->parent,
+    for (void* p : {(void*)bvh->nodes, (void*)bvh->tris, (void*)bvh->rec_of, (void*)bvh->child, (void*)bvh->range,
+                    (void*)bvh->parent,
                     (void*)bvh->box, (void*)bvh->by_depth, (void*)bvh->bounds, bvh->tl, (void*)bvh->inst})
         if (p) (void)hipFree(p);
     delete bvh;

@@ -2,9 +2,10 @@
 // triangle centroids (Karras, "Maximizing parallelism in the construction of
 // BVHs, octrees, and k-d trees", HPG 2012), built where the scene lives so a
 // dynamic scene does not cross PCIe every frame (Section 3.2 relies on the
-// driver's hierarchy; this one is the library's own).  One triangle per leaf;
-// the nodes take the layout the traversal reads (two child boxes in the
-// parent, padded by 2^-20 of the scene's largest coordinate).  A refit keeps
+// driver's hierarchy; this one is the library's own).  Subtrees of at most
+// four triangles (consecutive in Morton order) become leaves; the nodes take
+// the layout the traversal reads (two child boxes in the parent, padded by
+// 2^-20 of the scene's largest coordinate).  A refit keeps
 // the topology and recomputes triangles and boxes from new vertices.
 //
 // Depth: a node's common-prefix length (30 code bits, then 32 index bits for
@@ -104,9 +105,10 @@ __device__ __forceinline__ int prefix(const uint32_t* __restrict__ key, int n, i
     return 32 + __clz((uint32_t)i ^ (uint32_t)j);
 }
 
-// child references: internal node c >= 0, leaf k as ~k; parent[T - 1 + k] of leaf k
+// child references: internal node c >= 0, leaf k as ~k; parent[T - 1 + k] of
+// leaf k; range[i] = the sorted positions [lo, hi] node i covers
 __global__ __launch_bounds__(kB) void karras_kernel(const uint32_t* __restrict__ key, int n, int2* child,
-                                                    int* parent) {
+                                                    int* parent, int2* range) {
     const int i = blockIdx.x * kB + threadIdx.x;
     if (i >= n - 1) return;
     const int d = (prefix(key, n, i, i + 1) - prefix(key, n, i, i - 1)) >= 0 ? 1 : -1;
@@ -128,6 +130,7 @@ __global__ __launch_bounds__(kB) void karras_kernel(const uint32_t* __restrict__
     const int c0 = (lo == g) ? ~g : g;
     const int c1 = (hi == g + 1) ? ~(g + 1) : g + 1;
     child[i] = make_int2(c0, c1);
+    range[i] = make_int2(lo, hi);
     parent[c0 >= 0 ? c0 : (n - 1) + ~c0] = i;
     parent[c1 >= 0 ? c1 : (n - 1) + ~c1] = i;
     if (i == 0) parent[0] = -1;
@@ -190,8 +193,13 @@ __global__ __launch_bounds__(kB) void merge_kernel(const uint32_t* __restrict__ 
 }
 
 // ---- node records in the traversal's layout ----
-__global__ __launch_bounds__(kB) void emit_kernel(const int2* __restrict__ child, const float* __restrict__ box,
-                                                  uint32_t T, const float* __restrict__ bounds, float4* nodes) {
+// A subtree of at most kLeafMax triangles (consecutive in sorted order)
+// becomes one leaf of its parent; the nodes inside it are left unreferenced.
+constexpr int kLeafMax = 4;
+
+__global__ __launch_bounds__(kB) void emit_kernel(const int2* __restrict__ child, const int2* __restrict__ range,
+                                                  const float* __restrict__ box, uint32_t T,
+                                                  const float* __restrict__ bounds, float4* nodes) {
     const uint32_t i = blockIdx.x * kB + threadIdx.x;
     if (i >= T - 1) return;
     const float pad = ldexpf(fmaxf(bounds[6], 1e-6f), -20);
@@ -205,7 +213,13 @@ __global__ __launch_bounds__(kB) void emit_kernel(const int2* __restrict__ child
             lo[s][a] = box[6ull * n + a] - pad;
             hi[s][a] = box[6ull * n + 3 + a] + pad;
         }
-        ref[s] = r >= 0 ? r : ~(int)((uint32_t)~r << kLeafCountBits);  // leaf of one triangle
+        if (r < 0) {
+            ref[s] = ~(int)((uint32_t)~r << kLeafCountBits);  // leaf of one triangle
+        } else {
+            const int2 rg = range[r];
+            const int cnt = rg.y - rg.x + 1;
+            ref[s] = cnt <= kLeafMax ? ~(int)(((uint32_t)rg.x << kLeafCountBits) | (uint32_t)(cnt - 1)) : r;
+        }
     }
     float4* o = nodes + 4ull * i;
     o[0] = make_float4(lo[0][0], hi[0][0], lo[0][1], hi[0][1]);
@@ -254,13 +268,14 @@ dhr_status fill(dhr_ctx* ctx, dhr_bvh* b, const float* tris, const uint32_t* obj
         const uint32_t o = b->level_off[l], n = b->level_off[l + 1] - o;
         if (n) hipLaunchKernelGGL(merge_kernel, dim3(blocks(n)), dim3(kB), 0, s, b->by_depth + o, n, b->child, T, b->box);
     }
-    hipLaunchKernelGGL(emit_kernel, dim3(blocks(T - 1)), dim3(kB), 0, s, b->child, b->box, T, b->bounds, b->nodes);
+    hipLaunchKernelGGL(emit_kernel, dim3(blocks(T - 1)), dim3(kB), 0, s, b->child, b->range, b->box, T, b->bounds,
+                       b->nodes);
     return check_launch(ctx, what);
 }
 
 void release(dhr_bvh* b) {
-    for (void* p : {(void*)b->nodes, (void*)b->tris, (void*)b->rec_of, (void*)b->child, (void*)b->parent,
-                    (void*)b->box, (void*)b->by_depth, (void*)b->bounds})
+    for (void* p : {(void*)b->nodes, (void*)b->tris, (void*)b->rec_of, (void*)b->child, (void*)b->range,
+                    (void*)b->parent, (void*)b->box, (void*)b->by_depth, (void*)b->bounds})
         if (p) (void)hipFree(p);
     delete b;
 }
@@ -296,7 +311,7 @@ dhr_status dhr_build_bvh_device(dhr_ctx* ctx, const float* tris, const uint32_t*
     tmp_bytes = std::max(tmp_bytes, tmp_depth);
     bool ok = hipMalloc(&b->nodes, NI * 64) == hipSuccess && hipMalloc(&b->tris, 48ull * T) == hipSuccess &&
               hipMalloc(&b->rec_of, 4ull * T) == hipSuccess &&
-              hipMalloc(&b->child, sizeof(int2) * NI) == hipSuccess &&
+              hipMalloc(&b->child, sizeof(int2) * NI) == hipSuccess && hipMalloc(&b->range, sizeof(int2) * NI) == hipSuccess &&
               hipMalloc(&b->parent, sizeof(int) * (NI + T)) == hipSuccess &&
               hipMalloc(&b->box, 24ull * (NI + T)) == hipSuccess && hipMalloc(&b->by_depth, 4ull * NI) == hipSuccess &&
               hipMalloc(&b->bounds, 4ull * 7 * 1024) == hipSuccess && hipMalloc(&key, 4ull * T) == hipSuccess &&
@@ -322,7 +337,8 @@ dhr_status dhr_build_bvh_device(dhr_ctx* ctx, const float* tris, const uint32_t*
         if (hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, key, key2, val, order, (int)T, 0, 30, s) != hipSuccess)
             st = set_error(ctx, DHR_ERR_DEVICE, "dhr_build_bvh_device: sort failed");
         if (st == DHR_OK) {
-            hipLaunchKernelGGL(karras_kernel, dim3(blocks(T - 1)), dim3(kB), 0, s, key2, (int)T, b->child, b->parent);
+            hipLaunchKernelGGL(karras_kernel, dim3(blocks(T - 1)), dim3(kB), 0, s, key2, (int)T, b->child, b->parent,
+                               b->range);
             // internal nodes grouped by depth, deepest first, for the
             // level-by-level box pass
             hipLaunchKernelGGL(depth_kernel, dim3(blocks(NI)), dim3(kB), 0, s, b->parent, (uint32_t)NI, key);
@@ -368,7 +384,7 @@ dhr_status dhr_build_bvh_device(dhr_ctx* ctx, const float* tris, const uint32_t*
     b->info.n_tris = T;
     b->info.device_bytes = NI * 64 + 52ull * T;
     b->info.depth = depth;
-    b->info.max_leaf_size = 1;
+    b->info.max_leaf_size = T > 1 ? (uint32_t)std::min<uint32_t>(T, kLeafMax) : 1u;
     b->info.sah_cost = 0.0;
     b->info.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (depth - 1 > (uint32_t)kStack) {  // interior nodes on the longest path

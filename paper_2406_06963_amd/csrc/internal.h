@@ -35,6 +35,7 @@ struct dhr_bvh {
     // children of each internal node, parents of internal nodes and leaves,
     // per-node boxes and arrival counters of the bottom-up pass
     int2* child = nullptr;
+    int2* range = nullptr;        // [T - 1]: sorted triangle positions under each internal node
     int* parent = nullptr;        // [T - 1] internal, then [T] leaves
     float* box = nullptr;         // [T - 1 + T][6]
     uint32_t* by_depth = nullptr; // internal nodes ordered by depth, deepest level first

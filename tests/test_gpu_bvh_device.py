@@ -1,7 +1,8 @@
 """The device BVH build and refit (needs an MI355X).
 
-* Structure: every triangle sits in exactly one leaf; every stored child box
-  holds its subtree's triangles; depth within the traversal stack.
+* Structure: every triangle sits in exactly one leaf (of at most four);
+  every stored child box holds its subtree's triangles; depth within the
+  traversal stack.
 * Queries: visibility rays and the G-buffer on the device-built hierarchy
   give the oracle's results, exactly as the host-built one does.
 * Refit: after an object moves, the refitted hierarchy answers like the
@@ -47,7 +48,7 @@ def test_structure(B, ctx, name):
     bvh = device_bvh(B, ctx, sc.tris, sc.obj_id)
     info = bvh.info()
     T = sc.n_tris
-    assert info["n_tris"] == T and info["n_nodes"] == T - 1 and info["max_leaf_size"] == 1
+    assert info["n_tris"] == T and info["n_nodes"] == T - 1 and 1 <= info["max_leaf_size"] <= 4
     assert info["depth"] <= 65
     nodes, recs = B.dhr_bvh_export(ctx, bvh)
     nd = nodes.cpu().numpy().reshape(-1, 4, 4)
@@ -61,10 +62,10 @@ def test_structure(B, ctx, name):
 
     def bounds(ref):
         if ref < 0:
-            k = (~ref) >> 3
-            assert not seen[k]
-            seen[k] = True
-            return verts[k].min(0), verts[k].max(0)
+            k, cnt = (~ref) >> 3, ((~ref) & 7) + 1
+            assert cnt <= 4 and not seen[k:k + cnt].any()
+            seen[k:k + cnt] = True
+            return verts[k:k + cnt].min((0, 1)), verts[k:k + cnt].max((0, 1))
         lo = np.full(3, np.inf)
         hi = np.full(3, -np.inf)
         for s in range(2):
@@ -80,12 +81,13 @@ def test_structure(B, ctx, name):
     sys.setrecursionlimit(10000)
     bounds(0)
     assert seen.all()
-    # reported depth (levels, root and leaves included) equals the walked one
+    # reported depth (levels of the tree before small subtrees become leaves,
+    # root and leaves included) bounds the walked one
     depth, level = 0, [0]
     while level:
         depth += 1
         level = [int(c) for n in level for c in refs[n] if c >= 0]
-    assert info["depth"] == depth + 1
+    assert depth + 1 <= info["depth"]
 
 
 @pytest.mark.parametrize("preset,n_ao,n_shadow", [("tiny", 8, 4), ("room720", 1, 1), ("terrain1080", 1, 2)])
