@@ -33,7 +33,7 @@ struct BwdDesc {
     float2* grad_cv;        // [HW]
     float2* g0;             // adjoint ping-pong [HW] x 2
     float2* g1;
-    float4* coef;           // [HW] (A, B, c', E)
+    float4* coef;           // [HW] (A, B, c', 1 / E)
     float4* aux;            // [HW] (prefilter adjoint / sk, centre-role dc, K, 0)
     double* part;           // [sum over levels of the level's workgroups][3]
     uint32_t part_off[DHR_MAX_LEVELS + 1];  // first workgroup of each level in part
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_a_direct(const BwdBatch Bt
                 if (w > 0.0f && xn > 0.0f) s_n = fmaf(ww, hw_log2(xn) * 0.6931471805599453f, s_n);
             }
             const float Gb = g > 0.0f ? gbar / (2.0f * g) / sk : 0.0f;
-            D.coef[i] = make_float4(A, Bc, cpr, E);
+            D.coef[i] = make_float4(A, Bc, cpr, iE);
             D.aux[i] = make_float4(Gb, cbar_c, K2, 0.0f);
         }
     }
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_b_direct(const BwdBatch Bt
                 continue;
             }
             const float cp = cv[p].x;
-            const float iE = 1.0f / cf.w;
+            const float iE = cf.w;
             const float w = fused_weight(depth_coef(D.dz[p], a, b, s, sz, P.eps_z * np4.w), kNegLog2e * iE, np4.w, cp,
                                          f3(np4), sn, n4, cvq.x);
             const float wbar = h * (cf.x * (cvq.x - cf.z) - Kp) + 2.0f * cf.y * h * h * w * cvq.y;
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_b_direct(const BwdBatch Bt
 // The same two passes on row-class tiles (levels up to kAdjRowsMax): the
 // taps' geometry and inputs are staged in LDS once per workgroup, as in the
 // forward levels.  Taps outside the frame or on invalid pixels are staged
-// with a zero normal (their weight is zero) and, in pass B, E = 1 (every
+// with a zero normal (their weight is zero) and, in pass B, 1/E = 1 (every
 // term stays finite and vanishes).
 template <int LEVEL>
 __global__ __launch_bounds__(kSvgfBlock) void adjoint_a_rows(const BwdBatch Bt, const SvgfK P) {
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_a_rows(const BwdBatch Bt, 
                 if (w > 0.0f && xn > 0.0f) s_n = fmaf(ww, hw_log2(xn) * 0.6931471805599453f, s_n);
             }
             const float Gb = g > 0.0f ? gbar / (2.0f * g) / sk : 0.0f;
-            D.coef[i] = make_float4(A, Bc, cpr, E);
+            D.coef[i] = make_float4(A, Bc, cpr, iE);
             D.aux[i] = make_float4(Gb, cbar_c, K2, 0.0f);
         }
     }
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_a_rows(const BwdBatch Bt, 
     }
 }
 
-// Pass B staging: a centre pixel p's geometry, its coefficients (A, B, c', E)
+// Pass B staging: a centre pixel p's geometry, its coefficients (A, B, c', 1/E)
 // and (c_p, K_p, dz_p).
 struct StagedP {
     float4 nz, cf, ck;
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_b_rows(const BwdBatch Bt, 
             const float4 np4 = s_nz[e];
             const float4 ck = s_ck[e];
             const float cp = ck.x, Kp = ck.y;
-            const float iE = 1.0f / cf.w;
+            const float iE = cf.w;
             const float w = fused_weight(depth_coef(make_float2(ck.z, ck.w), a, b, s, sz, P.eps_z * np4.w),
                                          kNegLog2e * iE, np4.w, cp, f3(np4), sn, n4, cvq.x);
             const float wbar = h * (cf.x * (cvq.x - cf.z) - Kp) + 2.0f * cf.y * h * h * w * cvq.y;
