@@ -35,8 +35,8 @@ FLOPS_PER_TRI = 48       # Moller-Trumbore without division: 2 cross (18), 4 dot
 # kernel's sources when it was taken and is ignored once they change.
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_terrain1080.md")
 KERNEL_SOURCES = {
-    "trace_kernel": ["trace.hip", "device.h"],
-    "gbuffer_kernel": ["trace.hip", "device.h"],
+    "trace_kernel": ["trace.hip", "device.h", "camera.h"],
+    "gbuffer_kernel": ["trace.hip", "device.h", "camera.h"],
     "svgf_pass": ["svgf.hip", "svgf_common.h", "device.h"],
 }
 
@@ -243,9 +243,11 @@ def main():
     hist_s = [torch.empty(HW, 4, device=dev) for _ in range(2)]
     out_s = torch.empty(HW, device=dev)
     work_s = torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device=dev)
-    n2 = 10
-    e2 = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(n2)]
-    for k, f in enumerate(range(args.warmup + args.steps - n2 - 2, args.warmup + args.steps)):
+    f_end = args.warmup + args.steps
+    f_first = max(1, f_end - 12)          # two untimed frames, then up to 10 timed
+    n2 = f_end - f_first - 2
+    e2 = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(max(n2, 0))]
+    for k, f in enumerate(range(f_first, f_end)):
         cur, prv = gb[f % 2], gb[(f + 1) % 2]
         B.dhr_gbuffer(ctx, bvh, cams[f], cams[f - 1], W, H, cur["pos"], cur["nz"], cur["dz"], cur["mv"])
         B.dhr_trace_visibility(ctx, bvh, B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao,
@@ -265,15 +267,17 @@ def main():
         if k >= 2:
             e2[k - 2][1].record()
     torch.cuda.synchronize()
-    two_ms = sum(a.elapsed_time(b) for a, b in e2) / n2
-    line["svgf_ao_and_shadow"] = {"ms": two_ms, "mpix_s": 2 * HW / (two_ms / 1e3) / 1e6,
-                                  "vs_ao_only": two_ms / per["svgf"]}
+    if n2 > 0:
+        two_ms = sum(a.elapsed_time(b) for a, b in e2) / n2
+        line["svgf_ao_and_shadow"] = {"ms": two_ms, "mpix_s": 2 * HW / (two_ms / 1e3) / 1e6,
+                                      "vs_ao_only": two_ms / per["svgf"]}
 
     # the lighter filter (one level of the 3x3 kernel) beside the full one, each
     # with its own history over the same noisy frames; both scored against a
     # 64-ray AO estimate of the last frame
-    line["svgf_light"] = bench_light_filter(B, ctx, bvh, pr, cams, lights, gb, ao, sh, P,
-                                            range(max(1, args.warmup + args.steps - 16), args.warmup + args.steps))
+    lf = range(max(1, args.warmup + args.steps - 16), args.warmup + args.steps)
+    if len(lf) >= 3:
+        line["svgf_light"] = bench_light_filter(B, ctx, bvh, pr, cams, lights, gb, ao, sh, P, lf)
 
     # the hierarchy built on the device (linear BVH) and refitted, and the
     # ray passes on it, against the host SAH build used above
