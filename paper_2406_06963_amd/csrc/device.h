@@ -268,7 +268,7 @@ __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, fl
     const bool sz = __ballot(live && id.z < 0.0f) != 0;
     int sp = 0, node = 0;
     bool in = live;          // COUNT: this lane's ray hits the current node
-    uint32_t in_stack = 0;   // COUNT: the same for every stack entry
+    uint64_t in_stack = 0;   // COUNT: the same for every stack entry (up to 64)
     while (true) {
         if (node >= 0) {
             bool h0, h1;
@@ -283,7 +283,7 @@ __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, fl
                 const uint64_t f0 = __ballot(h0 && h1 && t0 <= t1);
                 const bool first0 = 2 * __popcll(f0) >= __popcll(m0 & m1);
                 if (COUNT) {
-                    in_stack = (in_stack & ~(1u << sp)) | ((first0 ? h1 : h0) ? 1u << sp : 0u);
+                    in_stack = (in_stack & ~(1ull << sp)) | ((first0 ? h1 : h0) ? 1ull << sp : 0ull);
                     in = first0 ? h0 : h1;
                 }
                 wstk[sp++] = first0 ? c1 : c0;
@@ -307,7 +307,7 @@ __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, fl
         }
         if (sp == 0) return;
         node = uniform(wstk[--sp]);
-        if (COUNT) in = (in_stack >> sp) & 1u;
+        if (COUNT) in = (in_stack >> sp) & 1ull;
     }
 }
 
