@@ -9,7 +9,9 @@ an iterated edge-aware spatial kernel driven by that variance.
 * T8  with all edge-stopping weights equal to one every level is a normalised
       dilated B3 convolution (scipy.ndimage.convolve);
 * T9  with a static camera the first frames after a reset are the exact
-      running mean (the 1/h ramp of the moving average);
+      running mean (the 1/h ramp of the moving average), and the time average
+      of the accumulated AO converges to the closed-form visibility of the
+      floor beside a wall;
 * T10 an integer-pixel motion shifts the history exactly; disocclusion,
       normal, plane-distance and id rejection reset it;
 * variance from moments is the sample variance of the accumulated samples;
@@ -182,6 +184,49 @@ def test_static_camera_running_mean(orc):
     prev = hist[:, 0].astype(np.float64)
     h = orc.svgf_temporal(P, W, H, n_ao, samples[0], pos, nz, mv, pos, nz, hist, 0.001)
     np.testing.assert_allclose(h[:, 0], prev + 0.2 * (samples[0] / n_ao - prev), atol=1e-6)
+
+
+def test_static_camera_converges_to_the_closed_form(orc):
+    # floor beside an infinite wall, static camera: the time average of the
+    # accumulated AO c' over many frames converges to each pixel's expected
+    # visibility, the closed form V(d / r) of the wall pin
+    from paper_2406_06963_amd import workloads as wl
+    sc = wl.scene_plane_wall(wall_x=0.0)
+    W, H = 40, 40
+    cam = wl.Camera((-0.7, 2.5, 2.0), (-0.7, 0.0, -0.3))
+    s = orc.Scene(sc.tris, sc.obj_id)
+    pos, nz, _, _ = orc.gbuffer(s, cam, None, W, H)
+    mv = np.zeros((W * H, 2), np.float32)
+    P = orc.svgf_params()
+    r, n_ao, F, skip = 1.0, 4, 240, 20
+    pix = float(cam.pix_angle(H))
+    hist, acc = None, np.zeros(W * H)
+    for f in range(F):
+        ao, _, _ = orc.trace(s, orc.trace_params(W, H, frame=f, seed=23, n_ao=n_ao, ao_radius=r, n_shadow=0), pos, nz)
+        hist = orc.svgf_temporal(P, W, H, n_ao, ao, pos, nz, mv, pos, nz, hist, pix).astype(np.float32)
+        if f >= skip:
+            acc += hist[:, 0]
+    est = acc / (F - skip)
+    floor = (orc.id_bits(pos) == 0) & (nz[:, 3] > 0)
+    d = -pos[:, 0].astype(np.float64)
+    a = np.clip(d / r, 0.0, 1.0)
+    V = 1.0 - (np.arccos(a) - a * np.sqrt(1.0 - a * a)) / np.pi
+    sel = floor & (d > 0.0)
+    bins = np.clip((d / r / 0.1).astype(int), 0, 12)
+    checked = 0
+    for b in range(13):
+        m = sel & (bins == b)
+        if m.sum() < 20:
+            continue
+        # the EMA's time average has about the variance of the plain sample
+        # mean over the window; a factor 2 covers the correlation left
+        sigma = 2.0 * np.sqrt((V[m] * (1 - V[m])).sum() / (n_ao * (F - skip))) / m.sum()
+        assert abs(est[m].mean() - V[m].mean()) <= 5 * sigma + 1e-12, (b, est[m].mean(), V[m].mean(), sigma)
+        checked += 1
+    assert checked >= 8
+    # per pixel too, well inside the noise of one pixel's window
+    per_sigma = 2.0 * np.sqrt(V[sel] * (1 - V[sel]) / (n_ao * (F - skip)))
+    assert (np.abs(est[sel] - V[sel]) <= 6 * per_sigma + 1e-12).mean() >= 0.999
 
 
 def test_integer_shift_moves_history_exactly(orc):
