@@ -609,26 +609,42 @@ def cpu_baseline(pr, scene, cams, lights, args):
     hist = None
     prev = None
     rays = 0
-    t_trace = t_all = 0.0
+    t_trace = t_svgf = t_all = 0.0
     f0 = args.warmup
-    for f in range(f0, f0 + args.cpu_frames):
+
+    def frame(f, hist, prev):
         ts = time.perf_counter()
         pos, nz, dz, mv = orc.gbuffer(so, cams[f], cams[f - 1], W, H)
         tt = time.perf_counter()
         P = orc.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao, ao_radius=pr.ao_radius,
                              n_shadow=pr.n_shadow, lights=lights)
         ao, sh, _ = orc.trace(so, P, pos, nz)
-        t_trace += time.perf_counter() - tt
+        tf = time.perf_counter()
         pix = np.float32(2 * math.tan(0.5 * cams[f].fov_y) / H)
         ref = orc.svgf_filter(Po, W, H, pr.n_ao, ao, pos, nz, dz, mv, prev[0] if prev else None,
                               prev[1] if prev else None, hist, pix)
-        t_all += time.perf_counter() - ts
-        hist = ref["hist_out"].astype(np.float32)
-        prev = (pos, nz)
-        rays += int((nz[:, 3] > 0).sum()) * (pr.n_ao + len(lights) * pr.n_shadow)
-    return {"value": rays / t_all / 1e6, "unit": "Mrays/s", "cores": orc.num_threads(), "kind": "oracle",
+        te = time.perf_counter()
+        n = int((nz[:, 3] > 0).sum()) * (pr.n_ao + len(lights) * pr.n_shadow)
+        return ref["hist_out"].astype(np.float32), (pos, nz), n, tf - tt, te - tf, te - ts
+
+    for f in range(f0, f0 + args.cpu_frames):
+        hist, prev, n, dt_trace, dt_svgf, dt = frame(f, hist, prev)
+        rays += n
+        t_trace += dt_trace
+        t_svgf += dt_svgf
+        t_all += dt
+    cores = orc.num_threads()
+    # one more frame on one thread
+    orc.set_num_threads(1)
+    try:
+        _, _, n1, _, _, dt1 = frame(f0 + args.cpu_frames, hist, prev)
+    finally:
+        orc.set_num_threads(cores)
+    return {"value": rays / t_all / 1e6, "unit": "Mrays/s", "cores": cores, "kind": "oracle",
             "sample": f"{args.cpu_frames} full {W}x{H} frames of the same workload (G-buffer, rays, SVGF in FP64)",
-            "trace_only_mrays_s": rays / t_trace / 1e6}
+            "trace_only_mrays_s": rays / t_trace / 1e6,
+            "svgf_only_mpix_s": args.cpu_frames * W * H / t_svgf / 1e6,
+            "single_thread": {"value": n1 / dt1 / 1e6, "unit": "Mrays/s", "frames": 1}}
 
 
 if __name__ == "__main__":
