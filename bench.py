@@ -173,6 +173,7 @@ def main():
     acc = {k: sum(a.elapsed_time(b) for a, b in ev[k]) for k in ev}
     ms_per_step = (t_end - t_start) * 1e3 / args.steps
     per = {k: acc[k] / args.steps for k in acc}
+    per_median = {k: float(np.median([a.elapsed_time(b) for a, b in ev[k]])) for k in ev}
 
     # valid pixels of the timed frames (untimed recount)
     valid = 0
@@ -230,6 +231,7 @@ def main():
         "trace_mrays_s": rays_per_step / trace_s / 1e6,
         "svgf_mpix_s": HW / svgf_s / 1e6,
         "pass_ms": per,
+        "pass_ms_median": per_median,
         "valid_frac": valid / args.steps / HW,
         "bvh": {"nodes": info["n_nodes"], "depth": info["depth"], "build_s": bvh_s,
                 "device_mb": info["device_bytes"] / 2 ** 20},
@@ -473,7 +475,10 @@ def bench_preset(B, ctx, name, steps, warmup=5):
                         f"shadow rays/px, {pr.levels}-level SVGF", "steps": steps,
             "pass_ms": {"gbuf": t[0], "trace": t[1], "svgf": t[2]},
             "trace_mrays_s": rays / (t[1] / 1e3) / 1e6, "svgf_mpix_s": HW / (t[2] / 1e3) / 1e6,
-            "step_mrays_s": rays / (sum(t) / 1e3) / 1e6}
+            "step_mrays_s": rays / (sum(t) / 1e3) / 1e6,
+            "roofline_svgf": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                              "achieved": svgf_bytes_per_px(pr.levels) * HW / (t[2] / 1e3) / 1e9,
+                              "frac": svgf_bytes_per_px(pr.levels) * HW / (t[2] / 1e3) / 1e9 / HBM_PEAK_GBS}}
 
 
 def bench_backward(B, ctx, n_frames):
