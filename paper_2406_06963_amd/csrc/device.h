@@ -141,40 +141,26 @@ __device__ __forceinline__ NodeRec load_node_uniform(const float4* __restrict__ 
                    ld_const(nodes, 4 * node + 3)};
 }
 
-// Slab test of both child boxes of a node against [0, tmax].  With OCT the
-// sign of every lane's inverse direction on each axis is the same (sx, sy, sz
-// true for negative): the entry and exit planes are then picked once per
-// wave instead of by a min and a max per lane.  Both forms give the same
-// result, since fma rounding is monotone in the plane coordinate.
-template <bool OCT>
-__device__ __forceinline__ void box_test(const NodeRec& n, bool sx, bool sy, bool sz, float3 id, float3 ood,
-                                         float tmax, bool& h0, bool& h1, float& tn0, float& tn1, int& c0, int& c1) {
+// Slab test of both child boxes of a node against [0, tmax]: per axis the
+// entry plane is the min and the exit plane the max of the two plane
+// distances.  (Picking the planes once per wave where every lane's direction
+// has the same signs saves the min and max, but the pick costs a vector move
+// and select per plane, or scalar-unit work that the loop's control flow
+// already keeps busy; both measured slower.)
+__device__ __forceinline__ void box_test(const NodeRec& n, float3 id, float3 ood, float tmax, bool& h0, bool& h1,
+                                         float& tn0, float& tn1, int& c0, int& c1) {
     const float4 a = n.a, b = n.b, c = n.c;
     const int4 ch = __builtin_bit_cast(int4, n.ch);
-    float a_in, a_out, b_in, b_out;
-    if (OCT) {
-        const float anx = fmaf(sx ? a.y : a.x, id.x, -ood.x), afx = fmaf(sx ? a.x : a.y, id.x, -ood.x);
-        const float any = fmaf(sy ? a.w : a.z, id.y, -ood.y), afy = fmaf(sy ? a.z : a.w, id.y, -ood.y);
-        const float anz = fmaf(sz ? c.y : c.x, id.z, -ood.z), afz = fmaf(sz ? c.x : c.y, id.z, -ood.z);
-        const float bnx = fmaf(sx ? b.y : b.x, id.x, -ood.x), bfx = fmaf(sx ? b.x : b.y, id.x, -ood.x);
-        const float bny = fmaf(sy ? b.w : b.z, id.y, -ood.y), bfy = fmaf(sy ? b.z : b.w, id.y, -ood.y);
-        const float bnz = fmaf(sz ? c.w : c.z, id.z, -ood.z), bfz = fmaf(sz ? c.z : c.w, id.z, -ood.z);
-        a_in = fmaxf(fmaxf(anx, any), fmaxf(anz, 0.0f));
-        a_out = fminf(fminf(afx, afy), fminf(afz, tmax));
-        b_in = fmaxf(fmaxf(bnx, bny), fmaxf(bnz, 0.0f));
-        b_out = fminf(fminf(bfx, bfy), fminf(bfz, tmax));
-    } else {
-        const float ax0 = fmaf(a.x, id.x, -ood.x), ax1 = fmaf(a.y, id.x, -ood.x);
-        const float ay0 = fmaf(a.z, id.y, -ood.y), ay1 = fmaf(a.w, id.y, -ood.y);
-        const float az0 = fmaf(c.x, id.z, -ood.z), az1 = fmaf(c.y, id.z, -ood.z);
-        const float bx0 = fmaf(b.x, id.x, -ood.x), bx1 = fmaf(b.y, id.x, -ood.x);
-        const float by0 = fmaf(b.z, id.y, -ood.y), by1 = fmaf(b.w, id.y, -ood.y);
-        const float bz0 = fmaf(c.z, id.z, -ood.z), bz1 = fmaf(c.w, id.z, -ood.z);
-        a_in = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
-        a_out = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tmax));
-        b_in = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
-        b_out = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tmax));
-    }
+    const float ax0 = fmaf(a.x, id.x, -ood.x), ax1 = fmaf(a.y, id.x, -ood.x);
+    const float ay0 = fmaf(a.z, id.y, -ood.y), ay1 = fmaf(a.w, id.y, -ood.y);
+    const float az0 = fmaf(c.x, id.z, -ood.z), az1 = fmaf(c.y, id.z, -ood.z);
+    const float bx0 = fmaf(b.x, id.x, -ood.x), bx1 = fmaf(b.y, id.x, -ood.x);
+    const float by0 = fmaf(b.z, id.y, -ood.y), by1 = fmaf(b.w, id.y, -ood.y);
+    const float bz0 = fmaf(c.z, id.z, -ood.z), bz1 = fmaf(c.w, id.z, -ood.z);
+    const float a_in = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
+    const float a_out = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tmax));
+    const float b_in = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
+    const float b_out = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tmax));
     h0 = a_in <= a_out;
     h1 = b_in <= b_out;
     tn0 = a_in;
@@ -258,14 +244,10 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // With COUNT, `cnt` tallies the work of this lane's own ray: the nodes and
 // leaves whose boxes it hits (a bit stack beside the wave's stack records
 // whether it hit each pushed child) and the triangles of those leaves.
-template <bool COUNT, bool OCT, class Leaf, class Done>
+template <bool COUNT, class Leaf, class Done>
 __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, float3 id, float3 ood,
                                             const float& tmax, bool live, int* wstk, Leaf visit_leaf, Done done,
                                             TravCount* cnt) {
-    // octant of the live lanes (used with OCT, where it is the same for all)
-    const bool sx = __ballot(live && id.x < 0.0f) != 0;
-    const bool sy = __ballot(live && id.y < 0.0f) != 0;
-    const bool sz = __ballot(live && id.z < 0.0f) != 0;
     int sp = 0, node = 0;
     bool in = live;          // COUNT: this lane's ray hits the current node
     uint64_t in_stack = 0;   // COUNT: the same for every stack entry (up to 64)
@@ -275,7 +257,7 @@ __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, fl
             float t0, t1;
             int c0, c1;
             if (COUNT && in) ++cnt->nodes;
-            box_test<OCT>(load_node_uniform(nodes, node), sx, sy, sz, id, ood, tmax, h0, h1, t0, t1, c0, c1);
+            box_test(load_node_uniform(nodes, node), id, ood, tmax, h0, h1, t0, t1, c0, c1);
             c0 = uniform(c0);
             c1 = uniform(c1);
             const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
@@ -311,14 +293,6 @@ __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, fl
     }
 }
 
-// True when the live lanes' inverse directions share one octant.
-__device__ __forceinline__ bool same_octant(float3 id, bool live) {
-    const uint64_t m = __ballot(live);
-    const uint64_t x = __ballot(live && id.x < 0.0f), y = __ballot(live && id.y < 0.0f),
-                   z = __ballot(live && id.z < 0.0f);
-    return (x == 0 || x == m) && (y == 0 || y == m) && (z == 0 || z == m);
-}
-
 // Any hit at 0 < t < r.tmax for the lanes with `live`; the others return false.
 template <bool COUNT = false>
 __device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const float4* __restrict__ tris, const Ray& r,
@@ -337,10 +311,7 @@ __device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const 
         }
     };
     auto done = [&] { return !__any(tmax >= 0.0f); };
-    if (same_octant(id, live))
-        packet_walk<COUNT, true>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt);
-    else
-        packet_walk<COUNT, false>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt);
+    packet_walk<COUNT>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt);
     return hit;
 }
 
@@ -365,10 +336,7 @@ __device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, con
         }
     };
     auto done = [] { return false; };
-    if (same_octant(id, live))
-        packet_walk<false, true>(nodes, id, ood, tbest, live, wstk, leaf, done, nullptr);
-    else
-        packet_walk<false, false>(nodes, id, ood, tbest, live, wstk, leaf, done, nullptr);
+    packet_walk<false>(nodes, id, ood, tbest, live, wstk, leaf, done, nullptr);
     if (!live) tbest = __builtin_inff();
     return best;
 }
@@ -411,10 +379,7 @@ __device__ __forceinline__ void walk_bottom(const float4* __restrict__ nodes, fl
     const float3 id = safe_inv(d);
     const float3 ood = f3(o.x * id.x, o.y * id.y, o.z * id.z);
     const bool live = tmax >= 0.0f;
-    if (same_octant(id, live))
-        packet_walk<false, true>(nodes, id, ood, tmax, live, wstk, leaf, done, nullptr);
-    else
-        packet_walk<false, false>(nodes, id, ood, tmax, live, wstk, leaf, done, nullptr);
+    packet_walk<false>(nodes, id, ood, tmax, live, wstk, leaf, done, nullptr);
 }
 
 // any_hit through a two-level hierarchy (`top` its top-level nodes); wstk2
@@ -444,10 +409,7 @@ __device__ __forceinline__ bool any_hit_2l(const float4* __restrict__ top, const
             walk_bottom(bottom_nodes(L, b), o, d, tmax, wstk2, leaf, done);
         }
     };
-    if (same_octant(id, live))
-        packet_walk<false, true>(top, id, ood, tmax, live, wstk, top_leaf, done, nullptr);
-    else
-        packet_walk<false, false>(top, id, ood, tmax, live, wstk, top_leaf, done, nullptr);
+    packet_walk<false>(top, id, ood, tmax, live, wstk, top_leaf, done, nullptr);
     return hit;
 }
 
@@ -486,10 +448,7 @@ __device__ __forceinline__ void closest_hit_2l(const float4* __restrict__ top, c
             walk_bottom(bottom_nodes(L, b), oo, dd, tbest, wstk2, leaf, done);
         }
     };
-    if (same_octant(id, live))
-        packet_walk<false, true>(top, id, ood, tbest, live, wstk, top_leaf, done, nullptr);
-    else
-        packet_walk<false, false>(top, id, ood, tbest, live, wstk, top_leaf, done, nullptr);
+    packet_walk<false>(top, id, ood, tbest, live, wstk, top_leaf, done, nullptr);
     if (!live) tbest = __builtin_inff();
 }
 
