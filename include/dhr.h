@@ -293,6 +293,25 @@ typedef struct {
 dhr_status dhr_trace_visibility_batch(dhr_ctx* ctx, const dhr_trace_job* jobs, uint32_t n_jobs,
                                       dhr_stream stream);
 
+/* G-buffer and visibility of a frame in one launch (Section 2.2: the server
+ * renders the G-buffer and traces the frame's visibility rays from it;
+ * Sections 3.1 and 3.2 for the rays).  Writes exactly what dhr_gbuffer
+ * followed by dhr_trace_visibility (debug_ray_bits NULL) writes, with the
+ * same arguments, byte for byte; each 16 x 8 pixel block's visibility rays
+ * start as soon as its own texels exist, so the few blocks whose primary
+ * rays take long walks (grazing views) overlap other blocks' work instead of
+ * leaving the device idle behind them.  params->W, H must equal W, H.
+ * Errors: as the two calls; UNSUPPORTED while work counters are set
+ * (dhr_set_trace_counters). */
+dhr_status dhr_gbuffer_trace(dhr_ctx* ctx, const dhr_bvh* bvh, const dhr_camera* cur, const dhr_camera* prev,
+                             uint32_t W, uint32_t H, const dhr_trace_params* params, float* pos, float* nz, float* dz,
+                             float* mv, uint8_t* ao_count, uint8_t* shadow_count, dhr_stream stream);
+/* The batched form: job k of each array describes one frame; trace_jobs[k]
+ * must name gbuffer_jobs[k]'s bvh, size, pos and nz (INVALID_ARG otherwise).
+ * Results are identical to the per-job calls. */
+dhr_status dhr_gbuffer_trace_batch(dhr_ctx* ctx, const dhr_gbuffer_job* gbuffer_jobs, const dhr_trace_job* trace_jobs,
+                                   uint32_t n_jobs, dhr_stream stream);
+
 /* ------------------------------------------------------------------------
  * Modified SVGF (Section 3.3).
  *

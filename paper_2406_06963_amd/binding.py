@@ -106,7 +106,8 @@ EXPORTS = ["dhr_create", "dhr_destroy", "dhr_last_error", "dhr_sync", "dhr_versi
            "dhr_trace_visibility_batch", "dhr_svgf_default_params", "dhr_svgf_filter", "dhr_svgf_spatial_forward",
            "dhr_svgf_backward", "dhr_svgf_workspace_bytes", "dhr_philox4x32_10", "dhr_set_trace_counters",
            "dhr_encode_frame", "dhr_build_bvh_device", "dhr_refit_bvh", "dhr_bvh_export",
-           "dhr_gbuffer_raster_workspace_bytes", "dhr_gbuffer_raster", "dhr_build_bvh_instanced"]
+           "dhr_gbuffer_raster_workspace_bytes", "dhr_gbuffer_raster", "dhr_build_bvh_instanced",
+           "dhr_gbuffer_trace", "dhr_gbuffer_trace_batch"]
 
 _lib = None
 
@@ -138,6 +139,9 @@ def load(path: str = LIB_PATH):
     L.dhr_trace_visibility.argtypes = [vp, vp, C.POINTER(dhr_trace_params), vp, vp, vp, vp, vp, vp]
     L.dhr_gbuffer_batch.argtypes = [vp, C.POINTER(dhr_gbuffer_job), u32, vp]
     L.dhr_trace_visibility_batch.argtypes = [vp, C.POINTER(dhr_trace_job), u32, vp]
+    L.dhr_gbuffer_trace.argtypes = [vp, vp, C.POINTER(dhr_camera), C.POINTER(dhr_camera), u32, u32,
+                                    C.POINTER(dhr_trace_params), vp, vp, vp, vp, vp, vp, vp]
+    L.dhr_gbuffer_trace_batch.argtypes = [vp, C.POINTER(dhr_gbuffer_job), C.POINTER(dhr_trace_job), u32, vp]
     L.dhr_svgf_default_params.argtypes = [C.POINTER(dhr_svgf_params)]
     L.dhr_svgf_default_params.restype = None
     L.dhr_svgf_filter.argtypes = [vp, C.POINTER(dhr_svgf_params), C.POINTER(dhr_svgf_frame), u32, vp]
@@ -352,10 +356,8 @@ def dhr_trace_visibility(ctx, bvh, params, pos, nz, ao_count, shadow_count, debu
     _check(ctx, st, "dhr_trace_visibility")
 
 
-def dhr_gbuffer_batch(ctx, jobs, stream=None):
-    """jobs: list of dicts(bvh, cur, prev, W, H, pos, nz, dz, mv)."""
+def _gbuffer_jobs(jobs):
     arr = (dhr_gbuffer_job * max(len(jobs), 1))()
-    keep = []
     for k, j in enumerate(jobs):
         a = arr[k]
         a.bvh = j["bvh"].handle
@@ -365,12 +367,10 @@ def dhr_gbuffer_batch(ctx, jobs, stream=None):
             a.has_prev = 1
         a.W, a.H = j["W"], j["H"]
         a.pos, a.nz, a.dz, a.mv = _ptr(j["pos"]), _ptr(j["nz"]), _ptr(j["dz"]), _ptr(j["mv"])
-        keep.append(j)
-    _check(ctx, load().dhr_gbuffer_batch(ctx.handle, arr, len(jobs), _stream(stream)), "dhr_gbuffer_batch")
+    return arr
 
 
-def dhr_trace_visibility_batch(ctx, jobs, stream=None):
-    """jobs: list of dicts(bvh, params, pos, nz, ao_count, shadow_count)."""
+def _trace_jobs(jobs):
     arr = (dhr_trace_job * max(len(jobs), 1))()
     for k, j in enumerate(jobs):
         a = arr[k]
@@ -378,8 +378,37 @@ def dhr_trace_visibility_batch(ctx, jobs, stream=None):
         a.params = j["params"]
         a.pos, a.nz = _ptr(j["pos"]), _ptr(j["nz"])
         a.ao_count, a.shadow_count = _ptr(j["ao_count"]), _ptr(j.get("shadow_count"))
-    _check(ctx, load().dhr_trace_visibility_batch(ctx.handle, arr, len(jobs), _stream(stream)),
+    return arr
+
+
+def dhr_gbuffer_batch(ctx, jobs, stream=None):
+    """jobs: list of dicts(bvh, cur, prev, W, H, pos, nz, dz, mv)."""
+    _check(ctx, load().dhr_gbuffer_batch(ctx.handle, _gbuffer_jobs(jobs), len(jobs), _stream(stream)),
+           "dhr_gbuffer_batch")
+
+
+def dhr_trace_visibility_batch(ctx, jobs, stream=None):
+    """jobs: list of dicts(bvh, params, pos, nz, ao_count, shadow_count)."""
+    _check(ctx, load().dhr_trace_visibility_batch(ctx.handle, _trace_jobs(jobs), len(jobs), _stream(stream)),
            "dhr_trace_visibility_batch")
+
+
+def dhr_gbuffer_trace(ctx, bvh, cur, prev, W, H, params, pos, nz, dz, mv, ao_count, shadow_count, stream=None):
+    c = camera(cur)
+    p = camera(prev) if prev is not None else None
+    st = load().dhr_gbuffer_trace(ctx.handle, bvh.handle, C.byref(c), C.byref(p) if p is not None else None, W, H,
+                                  C.byref(params), _ptr(pos), _ptr(nz), _ptr(dz), _ptr(mv), _ptr(ao_count),
+                                  _ptr(shadow_count), _stream(stream))
+    _check(ctx, st, "dhr_gbuffer_trace")
+
+
+def dhr_gbuffer_trace_batch(ctx, gbuffer_jobs, trace_jobs, stream=None):
+    """Two lists of the dicts dhr_gbuffer_batch and dhr_trace_visibility_batch take, job k of each one frame."""
+    n = len(gbuffer_jobs)
+    if len(trace_jobs) != n:
+        raise ValueError("dhr_gbuffer_trace_batch: the two job lists differ in length")
+    _check(ctx, load().dhr_gbuffer_trace_batch(ctx.handle, _gbuffer_jobs(gbuffer_jobs), _trace_jobs(trace_jobs), n,
+                                               _stream(stream)), "dhr_gbuffer_trace_batch")
 
 
 def dhr_svgf_workspace_bytes(W, H, params, which=0) -> int:

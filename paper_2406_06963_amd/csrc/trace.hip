@@ -119,40 +119,40 @@ __device__ __forceinline__ uint32_t pack_of(uint32_t nr) {
     return (nr % 8 == 0) ? 8 : (nr % 4 == 0) ? 4 : (nr % 2 == 0) ? 2 : 1;
 }
 
-// COUNT: the instrumented variant that also tallies rays, node visits, leaf
-// visits and triangle tests into `counters` (device uint64[4]).
+// Workgroup LDS of the visibility pass: the stack columns of its waves (two
+// per wave for two-level hierarchies), and the block's ray origins, normals
+// and per-pixel counts.
+template <bool TWO_LEVEL>
+struct TraceShared {
+    int stack[kStack * (kBlock / 64) * (TWO_LEVEL ? 2 : 1)];
+    float4 s_o[kBlock];   // the block's ray origins, w = 1 for a valid pixel
+    float4 s_n[kBlock];   // and normals
+    uint32_t s_cnt[kBlock];
+    unsigned long long s_bits[kBlock];
+};
+
+// The visibility rays of one 16 x 8 block (tile t of job D) from its
+// G-buffer texels p4, n4 (this lane's pixel (x, y), index i; `inside`
+// false for lanes beyond the image).  Every lane of the workgroup takes
+// part (barriers).  With COUNT, tc and n_rays tally this lane's work.
 template <bool COUNT, bool TWO_LEVEL>
-__global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsigned long long* counters) {
-    __shared__ int stack[kStack * (kBlock / 64) * (TWO_LEVEL ? 2 : 1)];
-    __shared__ float4 s_o[kBlock];   // the tile's ray origins, w = 1 for a valid pixel
-    __shared__ float4 s_n[kBlock];   // and normals
-    __shared__ uint32_t s_cnt[kBlock];
-    __shared__ unsigned long long s_bits[kBlock];
-    const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
-    const TraceDesc& D = B.d[j];
-    const uint32_t t = blockIdx.x - B.tile0[j];
+__device__ __forceinline__ void trace_block(const TraceDesc& D, uint32_t t, uint32_t x, uint32_t y, bool inside,
+                                            size_t i, float4 p4, float4 n4, TraceShared<TWO_LEVEL>& S, TravCount& tc,
+                                            uint32_t& n_rays) {
     const uint32_t tx0 = (t % D.tiles_x) * kTileW, ty0 = (t / D.tiles_x) * kTileH;
-    uint32_t x, y;
-    tile_pixel(t, D.tiles_x, x, y);
-    const bool inside = x < D.W && y < D.H;
     const size_t HW = (size_t)D.W * D.H;
-    const size_t i = inside ? (size_t)y * D.W + x : 0;
-    const float4 p4 = D.pos[i];
-    const float4 n4 = D.nz[i];
     const bool valid = inside && n4.w > 0.0f;
     const float3 n = f3(n4);
     const float3 p = f3(p4);
     float eps = D.eps_abs;
     if (!(eps > 0.0f)) eps = fmaxf(1e-3f * D.ao_r, fmaxf(fmaxf(fabsf(p.x), fabsf(p.y)), fabsf(p.z)) * 0x1p-17f);
     const float3 o = p + n * eps;
-    s_o[threadIdx.x] = make_float4(o.x, o.y, o.z, valid ? 1.0f : 0.0f);
-    s_n[threadIdx.x] = make_float4(n.x, n.y, n.z, 0.0f);
+    S.s_o[threadIdx.x] = make_float4(o.x, o.y, o.z, valid ? 1.0f : 0.0f);
+    S.s_n[threadIdx.x] = make_float4(n.x, n.y, n.z, 0.0f);
     __syncthreads();
-    TravCount tc;
-    uint32_t n_rays = 0;
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int* wstk = stack + w * kStack;
-    int* wstk2 = stack + (TWO_LEVEL ? (kBlock / 64 + w) * kStack : 0);
+    int* wstk = S.stack + w * kStack;
+    int* wstk2 = S.stack + (TWO_LEVEL ? (kBlock / 64 + w) * kStack : 0);
     TwoLevel L{};
     if (TWO_LEVEL) L = *D.tl;
 
@@ -162,8 +162,8 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsig
         uint32_t cnt = 0;
         uint64_t bits = 0;
         if (P > 1) {
-            s_cnt[threadIdx.x] = 0;
-            s_bits[threadIdx.x] = 0;
+            S.s_cnt[threadIdx.x] = 0;
+            S.s_bits[threadIdx.x] = 0;
             __syncthreads();
         }
         for (uint32_t it = 0; it < nr; ++it) {
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsig
                 px = tx0 + lx;
                 py = ty0 + ly;
             }
-            const float4 so = s_o[src], sn = s_n[src];
+            const float4 so = S.s_o[src], sn = S.s_n[src];
             const bool v = so.w > 0.0f;
             Ray r;
             bool decided, occ;
@@ -193,15 +193,15 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsig
                     ++cnt;
                     if (s < 64) bits |= 1ull << s;
                 } else {
-                    atomicAdd(&s_cnt[src], 1u);
-                    if (s < 64) atomicOr(&s_bits[src], 1ull << s);
+                    atomicAdd(&S.s_cnt[src], 1u);
+                    if (s < 64) atomicOr(&S.s_bits[src], 1ull << s);
                 }
             }
         }
         if (P > 1) {
             __syncthreads();
-            cnt = s_cnt[threadIdx.x];
-            bits = s_bits[threadIdx.x];
+            cnt = S.s_cnt[threadIdx.x];
+            bits = S.s_bits[threadIdx.x];
         }
         if (inside) {
             if (st == 0)
@@ -212,6 +212,23 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsig
         }
         __syncthreads();  // s_cnt / s_bits are reused by the next stream
     }
+}
+
+// COUNT: the instrumented variant that also tallies rays, node visits, leaf
+// visits and triangle tests into `counters` (device uint64[4]).
+template <bool COUNT, bool TWO_LEVEL>
+__global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsigned long long* counters) {
+    __shared__ TraceShared<TWO_LEVEL> S;
+    const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
+    const TraceDesc& D = B.d[j];
+    const uint32_t t = blockIdx.x - B.tile0[j];
+    uint32_t x, y;
+    tile_pixel(t, D.tiles_x, x, y);
+    const bool inside = x < D.W && y < D.H;
+    const size_t i = inside ? (size_t)y * D.W + x : 0;
+    TravCount tc;
+    uint32_t n_rays = 0;
+    trace_block<COUNT, TWO_LEVEL>(D, t, x, y, inside, i, D.pos[i], D.nz[i], S, tc, n_rays);
     if (COUNT) {
         // one vector atomic per lane (instrumented runs only)
         atomicAdd(counters + 0, (unsigned long long)n_rays);
@@ -221,29 +238,25 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsig
     }
 }
 
+// The G-buffer texel of pixel (x, y) of job D: the closest hit of the ray
+// through the pixel centre.  Lanes with live false (beyond the image) take
+// part in the walk without a ray.
 template <bool TWO_LEVEL>
-__global__ __launch_bounds__(kBlock) void gbuffer_kernel(const GbufBatch B) {
-    __shared__ int stack[kStack * (kBlock / 64) * (TWO_LEVEL ? 2 : 1)];
-    const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
-    const GbufDesc& D = B.d[j];
-    uint32_t x, y;
-    tile_pixel(blockIdx.x - B.tile0[j], D.tiles_x, x, y);
-    if (x >= D.W || y >= D.H) return;
-    const size_t i = (size_t)y * D.W + x;
+__device__ __forceinline__ void texel_of(const GbufDesc& D, uint32_t x, uint32_t y, bool live, int* wstk, int* wstk2,
+                                         float4& pos, float4& nz, float2& dz, float2& mv) {
     const CamD& C = D.cur;
     const float3 eye = f3(C.eye[0], C.eye[1], C.eye[2]);
     const float3 d = cam_dir(C, x + 0.5f, y + 0.5f);
     float t;
-    int* wstk = stack + (threadIdx.x >> 6) * kStack;
     if (!TWO_LEVEL) {
-        const int hit = closest_hit(D.nodes, D.tris, eye, d, true, t, wstk);
-        gbuffer_texel(C, D.prev, D.has_prev != 0, D.W, D.H, x, y, d, hit < 0 ? nullptr : D.tris + 3 * hit, t,
-                      D.pos[i], D.nz[i], D.dz[i], D.mv[i]);
+        const int hit = closest_hit(D.nodes, D.tris, eye, d, live, t, wstk);
+        gbuffer_texel(C, D.prev, D.has_prev != 0, D.W, D.H, x, y, d, hit < 0 ? nullptr : D.tris + 3 * hit, t, pos,
+                      nz, dz, mv);
         return;
     }
     const TwoLevel L = *D.tl;
     int inst, tri;
-    closest_hit_2l(D.nodes, L, eye, d, true, t, inst, tri, wstk, wstk + (kBlock / 64) * kStack);
+    closest_hit_2l(D.nodes, L, eye, d, live, t, inst, tri, wstk, wstk2);
     float4 rec[3];
     if (inst >= 0) {
         // the hit triangle in world space, with the instance's object id
@@ -257,8 +270,60 @@ __global__ __launch_bounds__(kBlock) void gbuffer_kernel(const GbufBatch B) {
         rec[1] = make_float4(w1.x, w1.y, w1.z, oid);
         rec[2] = make_float4(w2.x, w2.y, w2.z, 0.0f);
     }
-    gbuffer_texel(C, D.prev, D.has_prev != 0, D.W, D.H, x, y, d, inst < 0 ? nullptr : rec, t, D.pos[i], D.nz[i],
-                  D.dz[i], D.mv[i]);
+    gbuffer_texel(C, D.prev, D.has_prev != 0, D.W, D.H, x, y, d, inst < 0 ? nullptr : rec, t, pos, nz, dz, mv);
+}
+
+template <bool TWO_LEVEL>
+__global__ __launch_bounds__(kBlock) void gbuffer_kernel(const GbufBatch B) {
+    __shared__ int stack[kStack * (kBlock / 64) * (TWO_LEVEL ? 2 : 1)];
+    const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
+    const GbufDesc& D = B.d[j];
+    uint32_t x, y;
+    tile_pixel(blockIdx.x - B.tile0[j], D.tiles_x, x, y);
+    if (x >= D.W || y >= D.H) return;
+    const size_t i = (size_t)y * D.W + x;
+    int* wstk = stack + (threadIdx.x >> 6) * kStack;
+    texel_of<TWO_LEVEL>(D, x, y, true, wstk, wstk + (kBlock / 64) * kStack, D.pos[i], D.nz[i], D.dz[i], D.mv[i]);
+}
+
+// G-buffer and visibility of a frame in one launch: each workgroup writes the
+// texels of its 16 x 8 block, then traces the block's visibility rays from
+// them (the same block and pixel order as trace_kernel).  The long primary
+// walks of some blocks then overlap other blocks' visibility work instead of
+// leaving the device idle behind them.
+struct FrameDesc {
+    GbufDesc g;
+    TraceDesc t;
+};
+constexpr int kFrameMaxB = 6;
+using FrameBatch = Batch<FrameDesc, kFrameMaxB>;
+static_assert(sizeof(FrameBatch) <= 4000, "kernel arguments too large");
+
+template <bool TWO_LEVEL>
+__global__ __launch_bounds__(kBlock) void frame_kernel(const FrameBatch B) {
+    __shared__ TraceShared<TWO_LEVEL> S;
+    const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
+    const FrameDesc& F = B.d[j];
+    const uint32_t t = blockIdx.x - B.tile0[j];
+    uint32_t x, y;
+    tile_pixel(t, F.g.tiles_x, x, y);
+    const bool inside = x < F.g.W && y < F.g.H;
+    const size_t i = inside ? (size_t)y * F.g.W + x : 0;
+    const uint32_t w = threadIdx.x >> 6;
+    float4 pos, nz;
+    float2 dz, mv;
+    int* wstk = S.stack + w * kStack;
+    texel_of<TWO_LEVEL>(F.g, x, y, inside, wstk, TWO_LEVEL ? S.stack + (kBlock / 64 + w) * kStack : wstk, pos, nz, dz,
+                        mv);
+    if (inside) {
+        F.g.pos[i] = pos;
+        F.g.nz[i] = nz;
+        F.g.dz[i] = dz;
+        F.g.mv[i] = mv;
+    }
+    TravCount tc;
+    uint32_t n_rays = 0;
+    trace_block<false, TWO_LEVEL>(F.t, t, x, y, inside, i, pos, nz, S, tc, n_rays);
 }
 
 __global__ void philox_kernel(uint32_t k0, uint32_t k1, const uint4* __restrict__ ctr, uint4* __restrict__ out,
@@ -362,24 +427,30 @@ dhr_status launch_batches(dhr_ctx* ctx, const std::vector<D>& descs, const std::
     return DHR_OK;
 }
 
+dhr_status trace_desc_of(dhr_ctx* ctx, const dhr_trace_job& J, uint32_t k, uint64_t* bits, const char* what,
+                         TraceDesc* d) {
+    if (!J.bvh || J.bvh->ctx != ctx) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: bad bvh", what, k);
+    dhr_status st = check_trace_params(ctx, J.params);
+    if (st != DHR_OK) return st;
+    if (!J.pos || !J.nz || !J.ao_count || !aligned16(J.pos) || !aligned16(J.nz))
+        return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: null or misaligned buffer", what, k);
+    if (J.params.n_lights > 0 && !J.shadow_count)
+        return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: shadow_count is NULL", what, k);
+    if (bits && (J.params.n_ao > 64 || J.params.n_shadow > 64 || !aligned8(bits)))
+        return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: debug_ray_bits needs n <= 64 rays per stream", what);
+    fill_trace_desc(J.bvh, J.params, J.pos, J.nz, J.ao_count, J.shadow_count, bits, d);
+    return DHR_OK;
+}
+
 dhr_status trace_jobs(dhr_ctx* ctx, const dhr_trace_job* jobs, uint32_t n, const uint64_t* const* bits_per_job,
                       dhr_stream stream, const char* what) {
     std::vector<TraceDesc> descs(n);
     std::vector<uint32_t> tiles(n);
     for (uint32_t k = 0; k < n; ++k) {
-        const dhr_trace_job& J = jobs[k];
-        if (!J.bvh || J.bvh->ctx != ctx) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: bad bvh", what, k);
-        dhr_status st = check_trace_params(ctx, J.params);
-        if (st != DHR_OK) return st;
-        if (!J.pos || !J.nz || !J.ao_count || !aligned16(J.pos) || !aligned16(J.nz))
-            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: null or misaligned buffer", what, k);
-        if (J.params.n_lights > 0 && !J.shadow_count)
-            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: shadow_count is NULL", what, k);
         uint64_t* bits = bits_per_job ? const_cast<uint64_t*>(bits_per_job[k]) : nullptr;
-        if (bits && (J.params.n_ao > 64 || J.params.n_shadow > 64 || !aligned8(bits)))
-            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: debug_ray_bits needs n <= 64 rays per stream", what);
-        fill_trace_desc(J.bvh, J.params, J.pos, J.nz, J.ao_count, J.shadow_count, bits, &descs[k]);
-        tiles[k] = tiles_of(J.params.W, J.params.H);
+        dhr_status st = trace_desc_of(ctx, jobs[k], k, bits, what, &descs[k]);
+        if (st != DHR_OK) return st;
+        tiles[k] = tiles_of(jobs[k].params.W, jobs[k].params.H);
     }
     DeviceGuard g(ctx->device);
     unsigned long long* cnt = reinterpret_cast<unsigned long long*>(ctx->trace_counters);
@@ -402,32 +473,37 @@ dhr_status trace_jobs(dhr_ctx* ctx, const dhr_trace_job* jobs, uint32_t n, const
     return st;
 }
 
+dhr_status gbuf_desc_of(dhr_ctx* ctx, const dhr_gbuffer_job& J, uint32_t k, const char* what, GbufDesc* dp) {
+    if (!J.bvh || J.bvh->ctx != ctx) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: bad bvh", what, k);
+    if (!size_ok(J.W, J.H)) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: image %ux%u outside 1..16384", what, J.W, J.H);
+    if (!J.pos || !J.nz || !J.dz || !J.mv || !aligned16(J.pos) || !aligned16(J.nz) || !aligned8(J.dz) ||
+        !aligned8(J.mv))
+        return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: null or misaligned buffer", what, k);
+    GbufDesc& d = *dp;
+    std::memset(&d, 0, sizeof d);
+    if (!make_cam(J.cur, J.W, J.H, &d.cur) || (J.has_prev && !make_cam(J.prev, J.W, J.H, &d.prev)))
+        return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: degenerate camera", what, k);
+    d.nodes = J.bvh->nodes;
+    d.tris = J.bvh->tris;
+    d.tl = reinterpret_cast<const TwoLevel*>(J.bvh->tl);
+    d.pos = reinterpret_cast<float4*>(J.pos);
+    d.nz = reinterpret_cast<float4*>(J.nz);
+    d.dz = reinterpret_cast<float2*>(J.dz);
+    d.mv = reinterpret_cast<float2*>(J.mv);
+    d.W = J.W;
+    d.H = J.H;
+    d.tiles_x = (J.W + kTileW - 1) / kTileW;
+    d.has_prev = J.has_prev ? 1u : 0u;
+    return DHR_OK;
+}
+
 dhr_status gbuffer_jobs(dhr_ctx* ctx, const dhr_gbuffer_job* jobs, uint32_t n, dhr_stream stream, const char* what) {
     std::vector<GbufDesc> descs(n);
     std::vector<uint32_t> tiles(n);
     for (uint32_t k = 0; k < n; ++k) {
-        const dhr_gbuffer_job& J = jobs[k];
-        if (!J.bvh || J.bvh->ctx != ctx) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: bad bvh", what, k);
-        if (!size_ok(J.W, J.H)) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: image %ux%u outside 1..16384", what, J.W, J.H);
-        if (!J.pos || !J.nz || !J.dz || !J.mv || !aligned16(J.pos) || !aligned16(J.nz) || !aligned8(J.dz) ||
-            !aligned8(J.mv))
-            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: null or misaligned buffer", what, k);
-        GbufDesc& d = descs[k];
-        std::memset(&d, 0, sizeof d);
-        if (!make_cam(J.cur, J.W, J.H, &d.cur) || (J.has_prev && !make_cam(J.prev, J.W, J.H, &d.prev)))
-            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: job %u: degenerate camera", what, k);
-        d.nodes = J.bvh->nodes;
-        d.tris = J.bvh->tris;
-        d.tl = reinterpret_cast<const TwoLevel*>(J.bvh->tl);
-        d.pos = reinterpret_cast<float4*>(J.pos);
-        d.nz = reinterpret_cast<float4*>(J.nz);
-        d.dz = reinterpret_cast<float2*>(J.dz);
-        d.mv = reinterpret_cast<float2*>(J.mv);
-        d.W = J.W;
-        d.H = J.H;
-        d.tiles_x = (J.W + kTileW - 1) / kTileW;
-        d.has_prev = J.has_prev ? 1u : 0u;
-        tiles[k] = tiles_of(J.W, J.H);
+        dhr_status st = gbuf_desc_of(ctx, jobs[k], k, what, &descs[k]);
+        if (st != DHR_OK) return st;
+        tiles[k] = tiles_of(jobs[k].W, jobs[k].H);
     }
     DeviceGuard g(ctx->device);
     std::vector<GbufDesc> d1, d2;
@@ -441,6 +517,42 @@ dhr_status gbuffer_jobs(dhr_ctx* ctx, const dhr_gbuffer_job* jobs, uint32_t n, d
     if (!d1.empty()) st = launch_batches<GbufDesc, kGbufMaxB>(ctx, d1, t1, gbuffer_kernel<false>, kBlock, s, what);
     if (st == DHR_OK && !d2.empty())
         st = launch_batches<GbufDesc, kGbufMaxB>(ctx, d2, t2, gbuffer_kernel<true>, kBlock, s, what);
+    return st;
+}
+
+// Job k's G-buffer and its visibility in one launch (frame_kernel): the
+// visibility job must read the G-buffer job's own pos and nz, at its size,
+// through the same hierarchy.
+dhr_status frame_jobs(dhr_ctx* ctx, const dhr_gbuffer_job* gj, const dhr_trace_job* tj, uint32_t n, dhr_stream stream,
+                      const char* what) {
+    if (ctx->trace_counters)
+        return set_error(ctx, DHR_ERR_UNSUPPORTED, "%s: work counters cover dhr_trace_visibility only", what);
+    std::vector<FrameDesc> descs(n);
+    std::vector<uint32_t> tiles(n);
+    for (uint32_t k = 0; k < n; ++k) {
+        dhr_status st = gbuf_desc_of(ctx, gj[k], k, what, &descs[k].g);
+        if (st != DHR_OK) return st;
+        st = trace_desc_of(ctx, tj[k], k, nullptr, what, &descs[k].t);
+        if (st != DHR_OK) return st;
+        if (tj[k].bvh != gj[k].bvh || tj[k].params.W != gj[k].W || tj[k].params.H != gj[k].H ||
+            tj[k].pos != gj[k].pos || tj[k].nz != gj[k].nz)
+            return set_error(ctx, DHR_ERR_INVALID_ARG,
+                             "%s: job %u: visibility must read the G-buffer's own pos and nz (same bvh and size)",
+                             what, k);
+        tiles[k] = tiles_of(gj[k].W, gj[k].H);
+    }
+    DeviceGuard g(ctx->device);
+    std::vector<FrameDesc> d1, d2;
+    std::vector<uint32_t> t1, t2;
+    for (uint32_t k = 0; k < n; ++k) {
+        (descs[k].g.tl ? d2 : d1).push_back(descs[k]);
+        (descs[k].g.tl ? t2 : t1).push_back(tiles[k]);
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    dhr_status st = DHR_OK;
+    if (!d1.empty()) st = launch_batches<FrameDesc, kFrameMaxB>(ctx, d1, t1, frame_kernel<false>, kBlock, s, what);
+    if (st == DHR_OK && !d2.empty())
+        st = launch_batches<FrameDesc, kFrameMaxB>(ctx, d2, t2, frame_kernel<true>, kBlock, s, what);
     return st;
 }
 
@@ -488,6 +600,35 @@ dhr_status dhr_gbuffer_batch(dhr_ctx* ctx, const dhr_gbuffer_job* jobs, uint32_t
     if (!ctx) return DHR_ERR_INVALID_ARG;
     if (!jobs && n_jobs) return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_gbuffer_batch: jobs is NULL");
     return dhr::gbuffer_jobs(ctx, jobs, n_jobs, stream, "dhr_gbuffer_batch");
+}
+
+dhr_status dhr_gbuffer_trace(dhr_ctx* ctx, const dhr_bvh* bvh, const dhr_camera* cur, const dhr_camera* prev,
+                             uint32_t W, uint32_t H, const dhr_trace_params* params, float* pos, float* nz, float* dz,
+                             float* mv, uint8_t* ao_count, uint8_t* shadow_count, dhr_stream stream) {
+    if (!ctx) return DHR_ERR_INVALID_ARG;
+    if (!cur || !params) return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_gbuffer_trace: camera or params is NULL");
+    dhr_gbuffer_job g;
+    std::memset(&g, 0, sizeof g);
+    g.bvh = bvh;
+    g.cur = *cur;
+    if (prev) g.prev = *prev;
+    g.has_prev = prev != nullptr;
+    g.W = W;
+    g.H = H;
+    g.pos = pos;
+    g.nz = nz;
+    g.dz = dz;
+    g.mv = mv;
+    dhr_trace_job t{bvh, *params, pos, nz, ao_count, shadow_count};
+    return dhr::frame_jobs(ctx, &g, &t, 1, stream, "dhr_gbuffer_trace");
+}
+
+dhr_status dhr_gbuffer_trace_batch(dhr_ctx* ctx, const dhr_gbuffer_job* gbuffer_jobs, const dhr_trace_job* trace_jobs,
+                                   uint32_t n_jobs, dhr_stream stream) {
+    if (!ctx) return DHR_ERR_INVALID_ARG;
+    if ((!gbuffer_jobs || !trace_jobs) && n_jobs)
+        return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_gbuffer_trace_batch: jobs is NULL");
+    return dhr::frame_jobs(ctx, gbuffer_jobs, trace_jobs, n_jobs, stream, "dhr_gbuffer_trace_batch");
 }
 
 dhr_status dhr_philox4x32_10(dhr_ctx* ctx, uint32_t k0, uint32_t k1, const uint32_t* ctr, uint32_t* out, uint64_t n,
