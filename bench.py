@@ -35,6 +35,7 @@ FLOPS_PER_TRI = 48       # Moller-Trumbore without division: 2 cross (18), 4 dot
 # kernel's sources when it was taken and is ignored once they change.
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_terrain1080.md")
 KERNEL_SOURCES = {
+    "frame_kernel": ["trace.hip", "device.h", "camera.h"],
     "trace_kernel": ["trace.hip", "device.h", "camera.h"],
     "gbuffer_kernel": ["trace.hip", "device.h", "camera.h"],
     "svgf_pass": ["svgf.hip", "svgf_common.h", "device.h"],
@@ -140,20 +141,21 @@ def main():
 
     # one event pair per pass and timed step, all on the stream the kernels run on
     ev = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)] for k in ("gbuf", "trace", "svgf")}
+              for _ in range(args.steps)] for k in ("frame", "svgf", "gbuf", "trace")}
+
+    def tparams(f):
+        return B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao, ao_radius=pr.ao_radius,
+                              n_shadow=pr.n_shadow, lights=lights)
 
     def step(f, slot=None):
+        # G-buffer and visibility in one launch, then the filter
         cur, prv = gb[f % 2], gb[(f + 1) % 2]
         rec = (lambda k, e: ev[k][slot][e].record()) if slot is not None else (lambda k, e: None)
-        rec("gbuf", 0)
-        B.dhr_gbuffer(ctx, bvh, cams[f], cams[f - 1] if f > 0 else None, W, H,
-                      cur["pos"], cur["nz"], cur["dz"], cur["mv"])
-        rec("gbuf", 1)
-        tp = B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao, ao_radius=pr.ao_radius,
-                            n_shadow=pr.n_shadow, lights=lights)
-        rec("trace", 0)
-        B.dhr_trace_visibility(ctx, bvh, tp, cur["pos"], cur["nz"], ao, sh)
-        rec("trace", 1)
+        tp = tparams(f)
+        rec("frame", 0)
+        B.dhr_gbuffer_trace(ctx, bvh, cams[f], cams[f - 1] if f > 0 else None, W, H, tp,
+                            cur["pos"], cur["nz"], cur["dz"], cur["mv"], ao, sh)
+        rec("frame", 1)
         h_in = hist[(f + 1) % 2] if f > 0 else None
         fr = B.svgf_frame(W, H, pr.n_ao, ao, cur["pos"], cur["nz"], cur["dz"], cur["mv"],
                           prv["pos"] if f > 0 else None, prv["nz"] if f > 0 else None, h_in,
@@ -170,9 +172,20 @@ def main():
         step(f, k)
     torch.cuda.synchronize()
     t_end = time.perf_counter()
-    acc = {k: sum(a.elapsed_time(b) for a, b in ev[k]) for k in ev}
     ms_per_step = (t_end - t_start) * 1e3 / args.steps
-    per = {k: acc[k] / args.steps for k in acc}
+
+    # the same frames as two launches (dhr_gbuffer, then dhr_trace_visibility):
+    # the per-pass breakdown and the visibility kernel's own roofline
+    for k, f in enumerate(range(args.warmup, args.warmup + args.steps)):
+        g = gb[0]
+        ev["gbuf"][k][0].record()
+        B.dhr_gbuffer(ctx, bvh, cams[f], cams[f - 1], W, H, g["pos"], g["nz"], g["dz"], g["mv"])
+        ev["gbuf"][k][1].record()
+        ev["trace"][k][0].record()
+        B.dhr_trace_visibility(ctx, bvh, tparams(f), g["pos"], g["nz"], ao, sh)
+        ev["trace"][k][1].record()
+    torch.cuda.synchronize()
+    per = {k: sum(a.elapsed_time(b) for a, b in ev[k]) / args.steps for k in ev}
     per_median = {k: float(np.median([a.elapsed_time(b) for a, b in ev[k]])) for k in ev}
 
     # valid pixels of the timed frames (untimed recount)
@@ -183,20 +196,24 @@ def main():
         valid += int((g["nz"][:, 3] > 0).sum().item())
     rays_per_step = valid / args.steps * (pr.n_ao + len(lights) * pr.n_shadow)
 
-    # traversal work (instrumented kernel variant, untimed)
-    counts = None
+    # traversal work (instrumented kernel variants, untimed): the fused
+    # launch (primary and visibility rays) and the visibility launch alone
+    counts = counts_frame = None
     if not args.no_counters:
         c = torch.zeros(4, dtype=torch.int64, device=dev)
-        B.dhr_set_trace_counters(ctx, c)
+        cf = torch.zeros(4, dtype=torch.int64, device=dev)
         for f in range(args.warmup, args.warmup + args.steps):
             g = gb[0]
-            B.dhr_gbuffer(ctx, bvh, cams[f], cams[f - 1], W, H, g["pos"], g["nz"], g["dz"], g["mv"])
-            tp = B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao, ao_radius=pr.ao_radius,
-                                n_shadow=pr.n_shadow, lights=lights)
-            B.dhr_trace_visibility(ctx, bvh, tp, g["pos"], g["nz"], ao, sh)
+            B.dhr_set_trace_counters(ctx, cf)
+            B.dhr_gbuffer_trace(ctx, bvh, cams[f], cams[f - 1], W, H, tparams(f), g["pos"], g["nz"], g["dz"],
+                                g["mv"], ao, sh)
+            B.dhr_set_trace_counters(ctx, c)
+            B.dhr_trace_visibility(ctx, bvh, tparams(f), g["pos"], g["nz"], ao, sh)
         B.dhr_set_trace_counters(ctx, None)
         counts = [int(v) / args.steps for v in c.cpu().tolist()]
+        counts_frame = [int(v) / args.steps for v in cf.cpu().tolist()]
 
+    frame_s = per["frame"] / 1e3
     trace_s = per["trace"] / 1e3
     svgf_s = per["svgf"] / 1e3
     svgf_bytes = svgf_bytes_per_px(pr.levels) * HW
@@ -213,8 +230,18 @@ def main():
                       "kernel": "trace_visibility",
                       "traced_rays": counts[0], "node_visits": counts[1], "leaf_visits": counts[2],
                       "tri_tests": counts[3], "flops_per_node": FLOPS_PER_NODE, "flops_per_tri": FLOPS_PER_TRI}
-    dominant = "trace" if per["trace"] >= per["svgf"] else "svgf"
-    roofline = (roof_trace if (dominant == "trace" and roof_trace) else roof_svgf)
+    roof_frame = None
+    if counts_frame:
+        flops = counts_frame[1] * FLOPS_PER_NODE + counts_frame[3] * FLOPS_PER_TRI
+        ach = flops / frame_s / 1e12
+        roof_frame = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": ach / VALU_PEAK_TFLOPS, "traffic": pmc_traffic("frame_kernel"),
+                      "kernel": "gbuffer_trace (frame_kernel: primary + visibility rays)",
+                      "traced_rays": counts_frame[0], "node_visits": counts_frame[1],
+                      "leaf_visits": counts_frame[2], "tri_tests": counts_frame[3],
+                      "flops_per_node": FLOPS_PER_NODE, "flops_per_tri": FLOPS_PER_TRI}
+    dominant = "frame" if per["frame"] >= per["svgf"] else "svgf"
+    roofline = (roof_frame if (dominant == "frame" and roof_frame) else roof_svgf)
 
     line = {
         "metric": "AO+shadow Mrays/s and SVGF Mpix/s at 1080p; p99 frame latency, 64 clients",
@@ -232,12 +259,15 @@ def main():
         "svgf_mpix_s": HW / svgf_s / 1e6,
         "pass_ms": per,
         "pass_ms_median": per_median,
+        "pass_note": "frame = dhr_gbuffer_trace (the timed step: frame + svgf); gbuf and trace = the same "
+                     "frames as two launches, untimed for value",
         "valid_frac": valid / args.steps / HW,
         "bvh": {"nodes": info["n_nodes"], "depth": info["depth"], "build_s": bvh_s,
                 "device_mb": info["device_bytes"] / 2 ** 20},
         "roofline": roofline,
         "roofline_svgf": roof_svgf,
         "roofline_trace": roof_trace,
+        "roofline_frame": roof_frame,
     }
 
     # the light's visibility filtered by the same SVGF as a second channel
@@ -446,19 +476,21 @@ def bench_preset(B, ctx, name, steps, warmup=5):
     sh = torch.empty(max(len(lights), 1), HW, dtype=torch.uint8, device="cuda")
     out = torch.empty(HW, device="cuda")
     work = torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device="cuda")
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
     valid = 0
     for f in range(warmup + steps):
         cur, prv = gb[f % 2], gb[(f + 1) % 2]
         e = ev[f - warmup] if f >= warmup else None
+        tp = B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao, ao_radius=pr.ao_radius,
+                            n_shadow=pr.n_shadow, lights=lights)
+        prev = cams[f - 1] if f else None
         if e:
             e[0].record()
-        B.dhr_gbuffer(ctx, bvh, cams[f], cams[f - 1] if f else None, W, H, cur["pos"], cur["nz"], cur["dz"], cur["mv"])
-        if e:
+            B.dhr_gbuffer(ctx, bvh, cams[f], prev, W, H, cur["pos"], cur["nz"], cur["dz"], cur["mv"])
             e[1].record()
-        B.dhr_trace_visibility(ctx, bvh, B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao,
-                                                        ao_radius=pr.ao_radius, n_shadow=pr.n_shadow, lights=lights),
-                               cur["pos"], cur["nz"], ao, sh)
+            B.dhr_trace_visibility(ctx, bvh, tp, cur["pos"], cur["nz"], ao, sh)
+            e[4].record()
+        B.dhr_gbuffer_trace(ctx, bvh, cams[f], prev, W, H, tp, cur["pos"], cur["nz"], cur["dz"], cur["mv"], ao, sh)
         if e:
             e[2].record()
         fr = B.svgf_frame(W, H, pr.n_ao, ao, cur["pos"], cur["nz"], cur["dz"], cur["mv"],
@@ -469,16 +501,19 @@ def bench_preset(B, ctx, name, steps, warmup=5):
             e[3].record()
             valid += int((cur["nz"][:, 3] > 0).sum().item())
     torch.cuda.synchronize()
-    t = [sum(x[k].elapsed_time(x[k + 1]) for x in ev) / steps for k in range(3)]
+    # e0-e1 G-buffer, e1-e4 visibility (two launches, for the breakdown); e4-e2
+    # the same frame through dhr_gbuffer_trace; e2-e3 the filter
+    el = lambda a, b: sum(x[a].elapsed_time(x[b]) for x in ev) / steps
+    t_g, t_t, t_f, t_s = el(0, 1), el(1, 4), el(4, 2), el(2, 3)
     rays = valid / steps * (pr.n_ao + len(lights) * pr.n_shadow)
     return {"workload": f"{name}: {W}x{H}, {pr.scene} scene ({scene.n_tris} tris), {pr.n_ao} AO + {pr.n_shadow} "
                         f"shadow rays/px, {pr.levels}-level SVGF", "steps": steps,
-            "pass_ms": {"gbuf": t[0], "trace": t[1], "svgf": t[2]},
-            "trace_mrays_s": rays / (t[1] / 1e3) / 1e6, "svgf_mpix_s": HW / (t[2] / 1e3) / 1e6,
-            "step_mrays_s": rays / (sum(t) / 1e3) / 1e6,
+            "pass_ms": {"frame": t_f, "svgf": t_s, "gbuf": t_g, "trace": t_t},
+            "trace_mrays_s": rays / (t_t / 1e3) / 1e6, "svgf_mpix_s": HW / (t_s / 1e3) / 1e6,
+            "step_mrays_s": rays / ((t_f + t_s) / 1e3) / 1e6,
             "roofline_svgf": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
-                              "achieved": svgf_bytes_per_px(pr.levels) * HW / (t[2] / 1e3) / 1e9,
-                              "frac": svgf_bytes_per_px(pr.levels) * HW / (t[2] / 1e3) / 1e9 / HBM_PEAK_GBS}}
+                              "achieved": svgf_bytes_per_px(pr.levels) * HW / (t_s / 1e3) / 1e9,
+                              "frac": svgf_bytes_per_px(pr.levels) * HW / (t_s / 1e3) / 1e9 / HBM_PEAK_GBS}}
 
 
 def bench_backward(B, ctx, n_frames):

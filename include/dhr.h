@@ -301,8 +301,9 @@ dhr_status dhr_trace_visibility_batch(dhr_ctx* ctx, const dhr_trace_job* jobs, u
  * start as soon as its own texels exist, so the few blocks whose primary
  * rays take long walks (grazing views) overlap other blocks' work instead of
  * leaving the device idle behind them.  params->W, H must equal W, H.
- * Errors: as the two calls; UNSUPPORTED while work counters are set
- * (dhr_set_trace_counters). */
+ * While work counters are set (dhr_set_trace_counters) the counts cover the
+ * primary rays (one per pixel) and the visibility rays.
+ * Errors: as the two calls. */
 dhr_status dhr_gbuffer_trace(dhr_ctx* ctx, const dhr_bvh* bvh, const dhr_camera* cur, const dhr_camera* prev,
                              uint32_t W, uint32_t H, const dhr_trace_params* params, float* pos, float* nz, float* dz,
                              float* mv, uint8_t* ao_count, uint8_t* shadow_count, dhr_stream stream);
@@ -429,10 +430,12 @@ dhr_status dhr_svgf_backward(dhr_ctx* ctx, const dhr_svgf_params* params, const 
 uint64_t dhr_svgf_workspace_bytes(uint32_t W, uint32_t H, const dhr_svgf_params* params, int which);
 
 /* Instrumentation for measurement: while `counters` (device uint64[4], or
- * NULL to switch off) is set, trace calls on this context run a counting
- * variant of the kernel that adds (rays traced, interior-node visits, leaf
- * visits, triangle tests) into it.  Results are unchanged; the counting
- * variant is slower and is never the timed one. */
+ * NULL to switch off) is set, dhr_trace_visibility(_batch) and
+ * dhr_gbuffer_trace(_batch) on this context run a counting variant of their
+ * kernel that adds (rays traced, interior-node visits, leaf visits, triangle
+ * tests) into it; single-level hierarchies only (UNSUPPORTED otherwise).
+ * Results are unchanged; the counting variant is slower and is never the
+ * timed one. */
 dhr_status dhr_set_trace_counters(dhr_ctx* ctx, uint64_t* counters);
 
 /* ------------------------------------------------------------------------

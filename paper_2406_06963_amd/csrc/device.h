@@ -316,9 +316,11 @@ __device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const 
 }
 
 // Closest hit at t > 0 (ties: lowest original triangle index) for the lanes
-// with `live`; returns the position in leaf order, or -1.
+// with `live`; returns the position in leaf order, or -1.  COUNT: as for
+// any_hit.
+template <bool COUNT = false>
 __device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, const float4* __restrict__ tris, float3 o,
-                                           float3 d, bool live, float& tbest, int* wstk) {
+                                           float3 d, bool live, float& tbest, int* wstk, TravCount* cnt = nullptr) {
     const float3 id = safe_inv(d);
     const float3 ood = f3(o.x * id.x, o.y * id.y, o.z * id.z);
     int best = -1;
@@ -336,7 +338,7 @@ __device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, con
         }
     };
     auto done = [] { return false; };
-    packet_walk<false>(nodes, id, ood, tbest, live, wstk, leaf, done, nullptr);
+    packet_walk<COUNT>(nodes, id, ood, tbest, live, wstk, leaf, done, cnt);
     if (!live) tbest = __builtin_inff();
     return best;
 }

@@ -241,15 +241,15 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsig
 // The G-buffer texel of pixel (x, y) of job D: the closest hit of the ray
 // through the pixel centre.  Lanes with live false (beyond the image) take
 // part in the walk without a ray.
-template <bool TWO_LEVEL>
+template <bool TWO_LEVEL, bool COUNT = false>
 __device__ __forceinline__ void texel_of(const GbufDesc& D, uint32_t x, uint32_t y, bool live, int* wstk, int* wstk2,
-                                         float4& pos, float4& nz, float2& dz, float2& mv) {
+                                         float4& pos, float4& nz, float2& dz, float2& mv, TravCount* cnt = nullptr) {
     const CamD& C = D.cur;
     const float3 eye = f3(C.eye[0], C.eye[1], C.eye[2]);
     const float3 d = cam_dir(C, x + 0.5f, y + 0.5f);
     float t;
     if (!TWO_LEVEL) {
-        const int hit = closest_hit(D.nodes, D.tris, eye, d, live, t, wstk);
+        const int hit = closest_hit<COUNT>(D.nodes, D.tris, eye, d, live, t, wstk, cnt);
         gbuffer_texel(C, D.prev, D.has_prev != 0, D.W, D.H, x, y, d, hit < 0 ? nullptr : D.tris + 3 * hit, t, pos,
                       nz, dz, mv);
         return;
@@ -299,8 +299,10 @@ constexpr int kFrameMaxB = 6;
 using FrameBatch = Batch<FrameDesc, kFrameMaxB>;
 static_assert(sizeof(FrameBatch) <= 4000, "kernel arguments too large");
 
-template <bool TWO_LEVEL>
-__global__ __launch_bounds__(kBlock) void frame_kernel(const FrameBatch B) {
+// COUNT: the instrumented variant (single-level hierarchies), tallying the
+// primary and the visibility rays' work into `counters` as trace_kernel does.
+template <bool COUNT, bool TWO_LEVEL>
+__global__ __launch_bounds__(kBlock) void frame_kernel(const FrameBatch B, unsigned long long* counters) {
     __shared__ TraceShared<TWO_LEVEL> S;
     const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
     const FrameDesc& F = B.d[j];
@@ -313,17 +315,23 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(const FrameBatch B) {
     float4 pos, nz;
     float2 dz, mv;
     int* wstk = S.stack + w * kStack;
-    texel_of<TWO_LEVEL>(F.g, x, y, inside, wstk, TWO_LEVEL ? S.stack + (kBlock / 64 + w) * kStack : wstk, pos, nz, dz,
-                        mv);
+    TravCount tc;
+    texel_of<TWO_LEVEL, COUNT>(F.g, x, y, inside, wstk, TWO_LEVEL ? S.stack + (kBlock / 64 + w) * kStack : wstk, pos,
+                               nz, dz, mv, &tc);
     if (inside) {
         F.g.pos[i] = pos;
         F.g.nz[i] = nz;
         F.g.dz[i] = dz;
         F.g.mv[i] = mv;
     }
-    TravCount tc;
-    uint32_t n_rays = 0;
-    trace_block<false, TWO_LEVEL>(F.t, t, x, y, inside, i, pos, nz, S, tc, n_rays);
+    uint32_t n_rays = inside ? 1 : 0;
+    trace_block<COUNT, TWO_LEVEL>(F.t, t, x, y, inside, i, pos, nz, S, tc, n_rays);
+    if (COUNT) {
+        atomicAdd(counters + 0, (unsigned long long)n_rays);
+        atomicAdd(counters + 1, (unsigned long long)tc.nodes);
+        atomicAdd(counters + 2, (unsigned long long)tc.leaves);
+        atomicAdd(counters + 3, (unsigned long long)tc.tris);
+    }
 }
 
 __global__ void philox_kernel(uint32_t k0, uint32_t k1, const uint4* __restrict__ ctr, uint4* __restrict__ out,
@@ -525,8 +533,6 @@ dhr_status gbuffer_jobs(dhr_ctx* ctx, const dhr_gbuffer_job* jobs, uint32_t n, d
 // through the same hierarchy.
 dhr_status frame_jobs(dhr_ctx* ctx, const dhr_gbuffer_job* gj, const dhr_trace_job* tj, uint32_t n, dhr_stream stream,
                       const char* what) {
-    if (ctx->trace_counters)
-        return set_error(ctx, DHR_ERR_UNSUPPORTED, "%s: work counters cover dhr_trace_visibility only", what);
     std::vector<FrameDesc> descs(n);
     std::vector<uint32_t> tiles(n);
     for (uint32_t k = 0; k < n; ++k) {
@@ -548,11 +554,16 @@ dhr_status frame_jobs(dhr_ctx* ctx, const dhr_gbuffer_job* gj, const dhr_trace_j
         (descs[k].g.tl ? d2 : d1).push_back(descs[k]);
         (descs[k].g.tl ? t2 : t1).push_back(tiles[k]);
     }
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(ctx->trace_counters);
+    if (cnt && !d2.empty())
+        return set_error(ctx, DHR_ERR_UNSUPPORTED, "%s: work counters cover single-level hierarchies only", what);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     dhr_status st = DHR_OK;
-    if (!d1.empty()) st = launch_batches<FrameDesc, kFrameMaxB>(ctx, d1, t1, frame_kernel<false>, kBlock, s, what);
+    if (!d1.empty())
+        st = cnt ? launch_batches<FrameDesc, kFrameMaxB>(ctx, d1, t1, frame_kernel<true, false>, kBlock, s, what, cnt)
+                 : launch_batches<FrameDesc, kFrameMaxB>(ctx, d1, t1, frame_kernel<false, false>, kBlock, s, what, cnt);
     if (st == DHR_OK && !d2.empty())
-        st = launch_batches<FrameDesc, kFrameMaxB>(ctx, d2, t2, frame_kernel<true>, kBlock, s, what);
+        st = launch_batches<FrameDesc, kFrameMaxB>(ctx, d2, t2, frame_kernel<false, true>, kBlock, s, what, cnt);
     return st;
 }
 

@@ -4,8 +4,8 @@ Many thin clients send camera updates (the paper sends camera data to the
 server and tolerates it arriving up to 200 ms late, Section 4.1).  The server
 keeps each client's history resident in HBM (SVGF moments and length, the
 previous G-buffer and camera), and every tick packs the ready requests of
-different clients -- different scenes, resolutions and cameras -- into one
-ragged launch per pass (G-buffer, visibility, filter) on one of several
+different clients -- different scenes, resolutions and cameras -- into two
+ragged launches (G-buffer with visibility, then the filter) on one of several
 streams, so that work of consecutive batches overlaps on the device.
 
 Policy
@@ -293,8 +293,7 @@ class GpuExecutor:
                                        B.pix_angle(req.camera, spec.H), work=res["work"]))
             res["pending_slot"] = c
         with self.torch.cuda.stream(s):
-            B.dhr_gbuffer_batch(self.ctx, gjobs, stream=s)
-            B.dhr_trace_visibility_batch(self.ctx, tjobs, stream=s)
+            B.dhr_gbuffer_trace_batch(self.ctx, gjobs, tjobs, stream=s)
             B.dhr_svgf_filter(self.ctx, self.P, frames, stream=s)
             ev = self.torch.cuda.Event()
             ev.record(s)

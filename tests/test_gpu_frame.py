@@ -8,7 +8,8 @@ oracle; here the fused call is compared with them bit for bit:
 * two-level (instanced) and device-built hierarchies;
 * a batch longer than one launch holds, mixing sizes and hierarchy kinds;
 * its texels against the oracle's on the small scene, as for dhr_gbuffer;
-* mismatched jobs and set work counters are refused.
+* mismatched jobs are refused; the counting variant writes the same bytes
+  and counts one primary ray per pixel beyond the visibility rays.
 """
 import numpy as np
 import pytest
@@ -172,10 +173,34 @@ def test_fused_rejects_mismatched_jobs_and_counters(B, ctx):
         B.dhr_gbuffer_trace(ctx, bvh, cam, None, W, H, B.trace_params(W, H - 1, n_ao=1, ao_radius=1.0, n_shadow=1,
                                                                        lights=lights),
                             g["pos"], g["nz"], g["dz"], g["mv"], g["ao"], g["sh"])
-    cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
-    B.dhr_set_trace_counters(ctx, cnt)
+    with pytest.raises(ValueError):
+        B.dhr_gbuffer_trace_batch(ctx, [gjob, gjob], [tjob])
+
+
+def test_fused_counting_variant(B, ctx):
+    import torch
+    pr = wl.preset("tiny")
+    sc, _ = scene(pr.scene)
+    bvh = B.dhr_build_bvh(ctx, sc.tris, sc.obj_id)
+    cams = wl.camera_path(pr.camera, 2, sc)
+    lights = wl.lights_for(pr.scene)
+    W, H = pr.W, pr.H
+    tp = B.trace_params(W, H, frame=1, seed=pr.seed, n_ao=2, ao_radius=1.0, n_shadow=2, lights=lights)
+    ref = fused(B, ctx, bvh, cams[1], cams[0], W, H, tp, len(lights))
+    c_fused = torch.zeros(4, dtype=torch.int64, device="cuda")
+    c_trace = torch.zeros(4, dtype=torch.int64, device="cuda")
+    B.dhr_set_trace_counters(ctx, c_fused)
     try:
+        g = fused(B, ctx, bvh, cams[1], cams[0], W, H, tp, len(lights))
+        B.dhr_set_trace_counters(ctx, c_trace)
+        B.dhr_trace_visibility(ctx, bvh, tp, g["pos"], g["nz"], g["ao"], g["sh"])
         with pytest.raises(B.DhrError):
-            B.dhr_gbuffer_trace(ctx, bvh, cam, None, W, H, tp, g["pos"], g["nz"], g["dz"], g["mv"], g["ao"], g["sh"])
+            fused(B, ctx, _instanced(B, ctx), cams[1], cams[0], W, H, tp, len(lights))
     finally:
         B.dhr_set_trace_counters(ctx, None)
+    assert_same(g, ref, "counting variant")
+    cf, ct = c_fused.cpu().tolist(), c_trace.cpu().tolist()
+    print(f"fused counts {cf}, visibility alone {ct}", flush=True)
+    # one primary ray per pixel on top of the visibility rays; primary walks add node visits
+    assert cf[0] == ct[0] + W * H
+    assert cf[1] > ct[1] and cf[3] >= ct[3]
