@@ -28,18 +28,9 @@ __device__ __forceinline__ bool tap_consistent(float3 n, float3 p, float z, floa
     return dpl <= thr;
 }
 
-__global__ __launch_bounds__(kSvgfBlock) void temporal_kernel(const SvgfBatch B, const SvgfK P) {
-    const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
-    const SvgfDesc& D = B.d[j];
-    uint32_t x, y;
-    tile_xy(blockIdx.x - B.tile0[j], D.tiles_x, x, y);
-    if (x >= D.W || y >= D.H) return;
-    const size_t i = (size_t)y * D.W + x;
-    const float4 n4 = D.nz[i];
-    if (!(n4.w > 0.0f)) {
-        D.hist_out[i] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
-        return;
-    }
+// The accumulated history of one pixel (valid, index i); see temporal_kernel.
+__device__ __forceinline__ float4 accumulate(const SvgfDesc& D, const SvgfK& P, uint32_t x, uint32_t y, size_t i,
+                                             float4 n4) {
     // The blend and the moving averages run in FP64 and are rounded once to
     // the fp32 history: the variance downstream is a difference of moments
     // whose square root amplifies any rounding left in them.
@@ -97,12 +88,44 @@ __global__ __launch_bounds__(kSvgfBlock) void temporal_kernel(const SvgfBatch B,
     } else {
         h = make_float4((float)xs, (float)xs, (float)(xs * xs), 1.0f);
     }
-    D.hist_out[i] = h;
+    return h;
 }
 
-// Variance of level 0.  Workgroups with a pixel of short history stage the
-// moments and geometry of their 16 x 16 tile plus a 3-pixel rim in LDS for
-// the spatial fallback.
+// Temporal accumulation, and the level-0 input (c, var) of every pixel whose
+// variance needs no neighbours: invalid pixels, and valid ones with a history
+// of at least var_min_history frames (variance = difference of the stored
+// moments).  Each tile records whether it holds a pixel of shorter history;
+// only those tiles run the spatial fallback (variance_kernel).
+__global__ __launch_bounds__(kSvgfBlock) void temporal_kernel(const SvgfBatch B, const SvgfK P) {
+    const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
+    const SvgfDesc& D = B.d[j];
+    const uint32_t t = blockIdx.x - B.tile0[j];
+    uint32_t x, y;
+    tile_xy(t, D.tiles_x, x, y);
+    bool fallback = false;
+    if (x < D.W && y < D.H) {
+        const size_t i = (size_t)y * D.W + x;
+        const float4 n4 = D.nz[i];
+        float2* dst = level_buf(D, 0);
+        if (!(n4.w > 0.0f)) {
+            D.hist_out[i] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
+            dst[i] = make_float2(1.0f, 0.0f);
+        } else {
+            const float4 h = accumulate(D, P, x, y, i, n4);
+            D.hist_out[i] = h;
+            fallback = !(h.w >= (float)P.var_min_h);
+            // difference of the stored moments, exact in FP64, rounded once
+            if (!fallback) dst[i] = make_float2(h.x, (float)fmax(0.0, (double)h.z - (double)h.y * (double)h.y));
+        }
+    }
+    const int any = __syncthreads_or(fallback);
+    if (threadIdx.x == 0) D.fb[t] = any ? 1u : 0u;
+}
+
+// Variance of level 0 for the pixels of short history (the others were
+// written by temporal_kernel): only tiles that hold one do any work; they
+// stage the moments and geometry of their 16 x 16 tile plus a 3-pixel rim in
+// LDS for the spatial fallback.
 constexpr int kVarRim = 3;
 
 __global__ __launch_bounds__(kSvgfBlock) void variance_kernel(const SvgfBatch B, const SvgfK P) {
@@ -111,8 +134,10 @@ __global__ __launch_bounds__(kSvgfBlock) void variance_kernel(const SvgfBatch B,
     __shared__ float2 s_m[TW * TW];   // stored moments (m1, m2)
     const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
     const SvgfDesc& D = B.d[j];
+    const uint32_t t = blockIdx.x - B.tile0[j];
+    if (D.fb[t] == 0u) return;  // the whole workgroup: no pixel of short history
     uint32_t x, y;
-    tile_xy(blockIdx.x - B.tile0[j], D.tiles_x, x, y);
+    tile_xy(t, D.tiles_x, x, y);
     const int W = (int)D.W, H = (int)D.H;
     const bool inside = x < D.W && y < D.H;
     const size_t i = inside ? (size_t)y * D.W + x : 0;
@@ -142,17 +167,10 @@ __global__ __launch_bounds__(kSvgfBlock) void variance_kernel(const SvgfBatch B,
             });
         __syncthreads();
     }
-    if (!inside) return;
+    if (!fallback) return;
     float2* dst = level_buf(D, 0);
-    if (!valid) {
-        dst[i] = make_float2(1.0f, 0.0f);
-        return;
-    }
     float var;
-    if (!fallback) {
-        // difference of the stored moments, exact in FP64, rounded once
-        var = (float)fmax(0.0, (double)h.z - (double)h.y * (double)h.y);
-    } else {
+    {
         // pooled moments of the valid neighbours, depth/normal weights of level 0;
         // one pass with FP64 sums: var = sum w (mu2 - mu1^2) / sum w + (sum w mu1^2 / sum w - mbar^2)
         const int R = (int)P.R;
@@ -643,7 +661,8 @@ extern "C" {
 uint64_t dhr_svgf_workspace_bytes(uint32_t W, uint32_t H, const dhr_svgf_params* params, int which) {
     const uint64_t HW = (uint64_t)W * H;
     const uint32_t L = params ? params->levels : 5;
-    if (which == 0) return 2 * HW * 8 + HW * 4;   // (c, var) ping-pong + ke
+    if (which == 0) return 2 * HW * 8 + HW * 4 + (uint64_t)dhr::svgf_tiles(W, H) * 4;  // (c, var) ping-pong, ke,
+                                                                                     // tile fallback flags
     // adjoint: per-pixel coefficients (float4), two (c, v) adjoint buffers,
     // prefilter/centre terms (float4), and per-workgroup sigma partials (3
     // doubles per level and workgroup)
@@ -695,6 +714,7 @@ dhr_status dhr_svgf_filter(dhr_ctx* ctx, const dhr_svgf_params* params, const dh
         d.save = reinterpret_cast<float2*>(F.save);
         d.work = reinterpret_cast<float2*>(F.work);
         d.ke = reinterpret_cast<float*>(F.work) + (size_t)F.W * F.H * 4;
+        d.fb = reinterpret_cast<uint32_t*>(F.work) + (size_t)F.W * F.H * 5;
         d.pix = F.pix;
     }
     DeviceGuard g(ctx->device);

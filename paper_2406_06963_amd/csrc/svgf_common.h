@@ -37,6 +37,7 @@ struct SvgfDesc {
     float2* work;        // [2][HW]
     const float2* b0;    // level-0 input when it is not save[0]/work[0]
     float* ke;           // [HW] prefiltered AO-value coefficient of the current level (in work)
+    uint32_t* fb;        // [16 x 16 tiles] tile holds a pixel of short history (in work; filter only)
     float pix;
 };
 constexpr int kSvgfMaxB = 24;

@@ -41,7 +41,8 @@ def test_host_only_calls():
     assert B.dhr_version().startswith("dhr")
     p = B.svgf_params()
     assert p.levels == 5 and abs(p.alpha - 0.2) < 1e-7 and p.sigma_n[0] == 128.0 and p.kernel_width == 5
-    assert B.dhr_svgf_workspace_bytes(1920, 1080, p, 0) == 2 * 1920 * 1080 * 8 + 1920 * 1080 * 4
+    # (c, var) ping-pong, ke, one flag per 16 x 16 tile
+    assert B.dhr_svgf_workspace_bytes(1920, 1080, p, 0) == 2 * 1920 * 1080 * 8 + 1920 * 1080 * 4 + 120 * 68 * 4
     # creating a context without a device fails cleanly with a status
     import torch
     if not torch.cuda.is_available():
