@@ -32,12 +32,15 @@ __device__ __forceinline__ uint32_t fbits(float f) { return __float_as_uint(f); 
 // ---------------------------------------------------------------- RNG
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
 // multiply/xor S-box over a 4x32-bit counter, key bumped by the Weyl
-// constants of the golden ratio and sqrt(3)-1 between rounds.
+// constants of the golden ratio and sqrt(3)-1 between rounds.  Each product
+// is taken as one 32 x 32 -> 64-bit multiply (one v_mad_u64_u32 for both
+// halves instead of a low and a high multiply, both quarter rate).
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
