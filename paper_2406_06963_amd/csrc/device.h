@@ -150,8 +150,10 @@ __device__ __forceinline__ NodeRec load_node_uniform(const float4* __restrict__ 
 // has the same signs saves the min and max, but the pick costs a vector move
 // and select per plane, or scalar-unit work that the loop's control flow
 // already keeps busy; both measured slower.)
-__device__ __forceinline__ void box_test(const NodeRec& n, float3 id, float3 ood, float tmax, bool& h0, bool& h1,
-                                         float& tn0, float& tn1, int& c0, int& c1) {
+// Returns each child's entry and exit distance (entry clamped to 0); the
+// child is hit where entry <= min(exit, tmax).
+__device__ __forceinline__ void box_test(const NodeRec& n, float3 id, float3 ood, float& a_in, float& a_out,
+                                         float& b_in, float& b_out, int& c0, int& c1) {
     const float4 a = n.a, b = n.b, c = n.c;
     const int4 ch = __builtin_bit_cast(int4, n.ch);
     const float ax0 = fmaf(a.x, id.x, -ood.x), ax1 = fmaf(a.y, id.x, -ood.x);
@@ -160,14 +162,10 @@ __device__ __forceinline__ void box_test(const NodeRec& n, float3 id, float3 ood
     const float bx0 = fmaf(b.x, id.x, -ood.x), bx1 = fmaf(b.y, id.x, -ood.x);
     const float by0 = fmaf(b.z, id.y, -ood.y), by1 = fmaf(b.w, id.y, -ood.y);
     const float bz0 = fmaf(c.z, id.z, -ood.z), bz1 = fmaf(c.w, id.z, -ood.z);
-    const float a_in = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
-    const float a_out = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tmax));
-    const float b_in = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
-    const float b_out = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tmax));
-    h0 = a_in <= a_out;
-    h1 = b_in <= b_out;
-    tn0 = a_in;
-    tn1 = b_in;
+    a_in = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
+    a_out = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fmaxf(az0, az1));
+    b_in = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
+    b_out = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fmaxf(bz0, bz1));
     c0 = ch.x;
     c1 = ch.y;
 }
@@ -256,17 +254,22 @@ __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, fl
     uint64_t in_stack = 0;   // COUNT: the same for every stack entry (up to 64)
     while (true) {
         if (node >= 0) {
-            bool h0, h1;
-            float t0, t1;
+            float t0, x0, t1, x1;
             int c0, c1;
             if (COUNT && in) ++cnt->nodes;
-            box_test(load_node_uniform(nodes, node), id, ood, tmax, h0, h1, t0, t1, c0, c1);
+            box_test(load_node_uniform(nodes, node), id, ood, t0, x0, t1, x1, c0, c1);
             c0 = uniform(c0);
             c1 = uniform(c1);
-            const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
+            // hit masks: entry <= exit and entry <= tmax, each compare's own lane
+            // mask combined on the scalar unit (the distances are never NaN: the
+            // inverse direction is clamped to 1e20)
+            const uint64_t m0 = __ballot(t0 <= x0) & __ballot(t0 <= tmax);
+            const uint64_t m1 = __ballot(t1 <= x1) & __ballot(t1 <= tmax);
+            const bool h0 = COUNT && (t0 <= x0) && (t0 <= tmax), h1 = COUNT && (t1 <= x1) && (t1 <= tmax);
             if (m0 && m1) {
-                const uint64_t f0 = __ballot(h0 && h1 && t0 <= t1);
-                const bool first0 = 2 * __popcll(f0) >= __popcll(m0 & m1);
+                // lanes hitting both children, and those of them nearer child 0
+                const uint64_t both = m0 & m1, f0 = both & __ballot(t0 <= t1);
+                const bool first0 = 2 * __popcll(f0) >= __popcll(both);
                 if (COUNT) {
                     in_stack = (in_stack & ~(1ull << sp)) | ((first0 ? h1 : h0) ? 1ull << sp : 0ull);
                     in = first0 ? h0 : h1;
