@@ -396,11 +396,11 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, c
         int a, b;
         tap_ab<KR>(tp, a, b);
         const float kz = depth_coef(dzp, a, b, s, sz, eps_zp);
-        const float h = hk<KR>(a) * hk<KR>(b);
+        const float lh = lhk<KR>(a) + lhk<KR>(b);
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
             const int e = m ? c - b * TW - a : c + b * TW + a;
-            accumulate_tap(h, kz, ke, n4.w, cvp.x, np, sn, s_nz[e], s_cv[e], Dn, Sc, Sv);
+            accumulate_tap(lh, kz, ke, n4.w, cvp.x, np, sn, s_nz[e], s_cv[e], Dn, Sc, Sv);
         }
     }
     // deviation form: exact where every tap equals the centre (a constant
@@ -502,11 +502,11 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_rows_kernel(const SvgfBatch
         int a, b;
         tap_ab<KR>(tp, a, b);
         const float kz = depth_coef(dzp, a, b, s, sz, eps_zp);
-        const float h = hk<KR>(a) * hk<KR>(b);
+        const float lh = lhk<KR>(a) + lhk<KR>(b);
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
             const int e = m ? c - b * CW - s * a : c + b * CW + s * a;
-            accumulate_tap(h, kz, ke, n4.w, cvp.x, np, sn, s_nz[e], s_cv[e], Dn, Sc, Sv);
+            accumulate_tap(lh, kz, ke, n4.w, cvp.x, np, sn, s_nz[e], s_cv[e], Dn, Sc, Sv);
         }
     }
     const float inv = 1.0f / Dn;

@@ -128,6 +128,12 @@ __device__ __forceinline__ float k3(int a) { return a == 0 ? 0.5f : 0.25f; }
 // its mirror (-a, -b) is the matching tap before the centre.
 template <int KR>
 __device__ __forceinline__ float hk(int a) { return KR == 2 ? b3(a) : k3(a); }
+// log2 of the same weights (log2 3/8 = log2 3 - 3), added to a tap's
+// exponent instead of multiplying its weight
+template <int KR>
+__device__ __forceinline__ float lhk(int a) {
+    return KR == 2 ? (a == 0 ? -1.4150374992788438f : (a == 1 || a == -1 ? -2.0f : -4.0f)) : (a == 0 ? -1.0f : -2.0f);
+}
 template <int KR>
 constexpr int half_taps = ((2 * KR + 1) * (2 * KR + 1) - 1) / 2;
 template <int KR>
@@ -167,16 +173,17 @@ __device__ __forceinline__ float fused_weight(float kz, float ke, float zp, floa
 // One tap of a level whose staged neighbourhood holds a zero normal for
 // invalid pixels (so n_p . n_q = 0 and the weight vanishes): accumulates the
 // weight sum, the weighted deviation and the squared-weight variance.  The
-// normal term clamps n_p . n_q to [0, 1]; at 0 its log2 is -inf, the exponent
-// -inf and the weight exactly 0 with no test, provided sn > 0 (the parameter
-// block raises sigma_n = 0 to the smallest normal float, whose weight x^sn
-// rounds to 1 for every x > 0).
-__device__ __forceinline__ void accumulate_tap(float h, float kz, float ke, float zp, float cp, float3 np, float sn,
+// stencil weight enters as lh = log2 h in the exponent, h w = exp2(e + lh).
+// The normal term clamps n_p . n_q to [0, 1]; at 0 its log2 is -inf, the
+// exponent -inf and the weight exactly 0 with no test, provided sn > 0 (the
+// parameter block raises sigma_n = 0 to the smallest normal float, whose
+// weight x^sn rounds to 1 for every x > 0).
+__device__ __forceinline__ void accumulate_tap(float lh, float kz, float ke, float zp, float cp, float3 np, float sn,
                                                float4 nq, float2 cvq, float& Dn, float& Sc, float& Sv) {
     const float x = __builtin_amdgcn_fmed3f(dot3(np, f3(nq)), 0.0f, 1.0f);
     const float d = cvq.x - cp;
-    const float e = fmaf(kz, fabsf(zp - nq.w), fmaf(ke, fabsf(d), sn * hw_log2(x)));
-    const float hw = h * hw_exp2(e);
+    const float e = fmaf(kz, fabsf(zp - nq.w), fmaf(ke, fabsf(d), fmaf(sn, hw_log2(x), lh)));
+    const float hw = hw_exp2(e);
     Dn += hw;
     Sc = fmaf(hw, d, Sc);
     Sv = fmaf(hw * hw, cvq.y, Sv);
