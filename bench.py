@@ -94,7 +94,10 @@ def svgf_bytes_per_px(levels: int) -> int:
                 hist: 48) + hist_out 16                      = 105
       variance: hist 16 + nz 16 + (c, var) 8                 =  40
       level l : (c, var) 8 + nz 16 + dz 8 + output 8         =  40
-                (last level writes 4 bytes; level 0 also writes hist.c: +4)"""
+                (last level writes 4 bytes; level 0 also writes hist.c: +4)
+    These are the method's passes; the implementation writes most pixels'
+    level-0 input from the temporal kernel and runs the variance kernel on
+    short-history tiles only, so it moves fewer bytes than this figure."""
     return 105 + 40 + 40 * levels - 4 + 4
 
 
