@@ -135,50 +135,99 @@ def main():
     info = bvh.info()
     P = B.svgf_params(levels=pr.levels, alpha=pr.alpha)
 
-    gb = [B.gbuffer_tensors(W, H, dev) for _ in range(2)]
+    # three G-buffer / count slots: frame f+1 is written while frame f's
+    # filter reads frames f and f - 1
+    gb = [B.gbuffer_tensors(W, H, dev) for _ in range(3)]
     hist = [torch.empty(HW, 4, device=dev) for _ in range(2)]
-    ao = torch.empty(HW, dtype=torch.uint8, device=dev)
-    sh = torch.empty(len(lights), HW, dtype=torch.uint8, device=dev)
+    aos = [torch.empty(HW, dtype=torch.uint8, device=dev) for _ in range(3)]
+    shs = [torch.empty(len(lights), HW, dtype=torch.uint8, device=dev) for _ in range(3)]
+    ao, sh = aos[0], shs[0]          # the single-frame runs below
     out = torch.empty(HW, device=dev)
     work = torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device=dev)
 
-    # one event pair per pass and timed step, all on the stream the kernels run on
+    # one event pair per pass and timed step, each on the stream its kernels run on
     ev = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)] for k in ("frame", "svgf", "gbuf", "trace")}
+              for _ in range(args.steps)] for k in ("frame", "svgf", "frame_seq", "svgf_seq", "gbuf", "trace")}
 
     def tparams(f):
         return B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao, ao_radius=pr.ao_radius,
                               n_shadow=pr.n_shadow, lights=lights)
 
-    def step(f, slot=None):
-        # G-buffer and visibility in one launch, then the filter
-        cur, prv = gb[f % 2], gb[(f + 1) % 2]
-        rec = (lambda k, e: ev[k][slot][e].record()) if slot is not None else (lambda k, e: None)
-        tp = tparams(f)
-        rec("frame", 0)
-        B.dhr_gbuffer_trace(ctx, bvh, cams[f], cams[f - 1] if f > 0 else None, W, H, tp,
-                            cur["pos"], cur["nz"], cur["dz"], cur["mv"], ao, sh)
-        rec("frame", 1)
-        h_in = hist[(f + 1) % 2] if f > 0 else None
-        fr = B.svgf_frame(W, H, pr.n_ao, ao, cur["pos"], cur["nz"], cur["dz"], cur["mv"],
-                          prv["pos"] if f > 0 else None, prv["nz"] if f > 0 else None, h_in,
-                          hist[f % 2], out, B.pix_angle(cams[f], H), work=work)
-        rec("svgf", 0)
-        B.dhr_svgf_filter(ctx, P, [fr])
-        rec("svgf", 1)
+    tps = [tparams(f) for f in range(nfr)]
 
-    for f in range(args.warmup):
-        step(f)
+    def launch_frame(f, s):
+        # G-buffer and visibility of frame f in one launch
+        g = gb[f % 3]
+        B.dhr_gbuffer_trace(ctx, bvh, cams[f], cams[f - 1] if f > 0 else None, W, H, tps[f],
+                            g["pos"], g["nz"], g["dz"], g["mv"], aos[f % 3], shs[f % 3], stream=s)
+
+    def launch_filter(f, s):
+        g, p = gb[f % 3], gb[(f - 1) % 3]
+        fr = B.svgf_frame(W, H, pr.n_ao, aos[f % 3], g["pos"], g["nz"], g["dz"], g["mv"],
+                          p["pos"] if f > 0 else None, p["nz"] if f > 0 else None,
+                          hist[(f + 1) % 2] if f > 0 else None, hist[f % 2], out, B.pix_angle(cams[f], H), work=work)
+        B.dhr_svgf_filter(ctx, P, [fr], stream=s)
+
+    # default-priority streams: frame f + 1's G-buffer + visibility launch
+    # overlaps frame f's filter, as a renderer (or the serving loop) runs them
+    s_frame, s_filt = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def run(n0, n1, timed=False):
+        rec = (lambda k, f, e, s: ev[k][f - n0][e].record(s)) if timed else (lambda k, f, e, s: None)
+        s_frame.wait_stream(torch.cuda.current_stream())
+        s_filt.wait_stream(torch.cuda.current_stream())
+        done = {}
+
+        def frame(f):
+            rec("frame", f, 0, s_frame)
+            launch_frame(f, s_frame)
+            rec("frame", f, 1, s_frame)
+
+        frame(n0)
+        for f in range(n0, n1):
+            ready = torch.cuda.Event()
+            ready.record(s_frame)
+            s_filt.wait_event(ready)                 # filter f after frame f
+            rec("svgf", f, 0, s_filt)
+            launch_filter(f, s_filt)
+            rec("svgf", f, 1, s_filt)
+            if f + 1 < n1:
+                if f > n0:
+                    s_frame.wait_event(done[f - 1])  # slot (f + 1) % 3 is filter f - 1's previous frame
+                frame(f + 1)
+            d = torch.cuda.Event()
+            d.record(s_filt)
+            done[f] = d
+        torch.cuda.current_stream().wait_stream(s_frame)
+        torch.cuda.current_stream().wait_stream(s_filt)
+
+    run(0, args.warmup)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for k, f in enumerate(range(args.warmup, args.warmup + args.steps)):
-        step(f, k)
+    run(args.warmup, args.warmup + args.steps, timed=True)
     torch.cuda.synchronize()
     t_end = time.perf_counter()
     ms_per_step = (t_end - t_start) * 1e3 / args.steps
 
-    # the same frames as two launches (dhr_gbuffer, then dhr_trace_visibility):
-    # the per-pass breakdown and the visibility kernel's own roofline
+    # the same frames again, one at a time on one stream from the same
+    # history (the per-pass times without overlap), then as two launches
+    # (dhr_gbuffer, then dhr_trace_visibility): the per-pass breakdown and the
+    # visibility kernel's own roofline
+    cs = torch.cuda.current_stream()
+    for f in range(args.warmup):
+        launch_frame(f, cs)
+        launch_filter(f, cs)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter()
+    for k, f in enumerate(range(args.warmup, args.warmup + args.steps)):
+        ev["frame_seq"][k][0].record()
+        launch_frame(f, cs)
+        ev["frame_seq"][k][1].record()
+        ev["svgf_seq"][k][0].record()
+        launch_filter(f, cs)
+        ev["svgf_seq"][k][1].record()
+    torch.cuda.synchronize()
+    ms_per_step_seq = (time.perf_counter() - t_seq) * 1e3 / args.steps
     for k, f in enumerate(range(args.warmup, args.warmup + args.steps)):
         g = gb[0]
         ev["gbuf"][k][0].record()
@@ -216,9 +265,9 @@ def main():
         counts = [int(v) / args.steps for v in c.cpu().tolist()]
         counts_frame = [int(v) / args.steps for v in cf.cpu().tolist()]
 
-    frame_s = per["frame"] / 1e3
+    frame_s = per["frame"] / 1e3           # timed launches (overlapping the filter)
     trace_s = per["trace"] / 1e3
-    svgf_s = per["svgf"] / 1e3
+    svgf_s = per["svgf_seq"] / 1e3         # the filter alone (its timed span shares the device)
     svgf_bytes = svgf_bytes_per_px(pr.levels) * HW
     roof_svgf = {"bound": "hbm", "achieved": svgf_bytes / svgf_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": svgf_bytes / svgf_s / 1e9 / HBM_PEAK_GBS, "traffic": pmc_traffic("svgf_pass"),
@@ -233,17 +282,22 @@ def main():
                       "kernel": "trace_visibility",
                       "traced_rays": counts[0], "node_visits": counts[1], "leaf_visits": counts[2],
                       "tri_tests": counts[3], "flops_per_node": FLOPS_PER_NODE, "flops_per_tri": FLOPS_PER_TRI}
-    roof_frame = None
+    roof_frame = roof_frame_seq = None
     if counts_frame:
         flops = counts_frame[1] * FLOPS_PER_NODE + counts_frame[3] * FLOPS_PER_TRI
         ach = flops / frame_s / 1e12
         roof_frame = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                       "frac": ach / VALU_PEAK_TFLOPS, "traffic": pmc_traffic("frame_kernel"),
-                      "kernel": "gbuffer_trace (frame_kernel: primary + visibility rays)",
+                      "kernel": "gbuffer_trace (frame_kernel: primary + visibility rays; its timed launches "
+                                "overlap the previous frame's filter)",
                       "traced_rays": counts_frame[0], "node_visits": counts_frame[1],
                       "leaf_visits": counts_frame[2], "tri_tests": counts_frame[3],
                       "flops_per_node": FLOPS_PER_NODE, "flops_per_tri": FLOPS_PER_TRI}
-    dominant = "frame" if per["frame"] >= per["svgf"] else "svgf"
+        ach_seq = flops / (per["frame_seq"] / 1e3) / 1e12
+        roof_frame_seq = {"bound": "alu", "achieved": ach_seq, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": ach_seq / VALU_PEAK_TFLOPS, "kernel": "frame_kernel, launched alone"}
+    # the dominant kernel: the larger of the two passes run one at a time
+    dominant = "frame" if per["frame_seq"] >= per["svgf_seq"] else "svgf"
     roofline = (roof_frame if (dominant == "frame" and roof_frame) else roof_svgf)
 
     line = {
@@ -262,8 +316,11 @@ def main():
         "svgf_mpix_s": HW / svgf_s / 1e6,
         "pass_ms": per,
         "pass_ms_median": per_median,
-        "pass_note": "frame = dhr_gbuffer_trace (the timed step: frame + svgf); gbuf and trace = the same "
-                     "frames as two launches, untimed for value",
+        "ms_per_step_sequential": ms_per_step_seq,
+        "pass_note": "timed steps: frame = dhr_gbuffer_trace on one stream, svgf = dhr_svgf_filter on a second, "
+                     "frame f + 1 overlapping frame f's filter (so svgf is a span, not a kernel time); *_seq = "
+                     "the same frames one at a time on one stream; gbuf and trace = the same frames as two "
+                     "launches (untimed for value)",
         "valid_frac": valid / args.steps / HW,
         "bvh": {"nodes": info["n_nodes"], "depth": info["depth"], "build_s": bvh_s,
                 "device_mb": info["device_bytes"] / 2 ** 20},
@@ -271,6 +328,7 @@ def main():
         "roofline_svgf": roof_svgf,
         "roofline_trace": roof_trace,
         "roofline_frame": roof_frame,
+        "roofline_frame_sequential": roof_frame_seq,
     }
 
     # the light's visibility filtered by the same SVGF as a second channel
@@ -305,7 +363,7 @@ def main():
     if n2 > 0:
         two_ms = sum(a.elapsed_time(b) for a, b in e2) / n2
         line["svgf_ao_and_shadow"] = {"ms": two_ms, "mpix_s": 2 * HW / (two_ms / 1e3) / 1e6,
-                                      "vs_ao_only": two_ms / per["svgf"]}
+                                      "vs_ao_only": two_ms / per["svgf_seq"]}
 
     # the lighter filter (one level of the 3x3 kernel) beside the full one, each
     # with its own history over the same noisy frames; both scored against a
