@@ -567,11 +567,27 @@ def bench_preset(B, ctx, name, steps, warmup=5):
     el = lambda a, b: sum(x[a].elapsed_time(x[b]) for x in ev) / steps
     t_g, t_t, t_f, t_s = el(0, 1), el(1, 4), el(4, 2), el(2, 3)
     rays = valid / steps * (pr.n_ao + len(lights) * pr.n_shadow)
+    # the fused kernel's traversal work on the timed frames (counting variant, untimed)
+    c = torch.zeros(4, dtype=torch.int64, device="cuda")
+    B.dhr_set_trace_counters(ctx, c)
+    for f in range(warmup, warmup + steps):
+        g = gb[0]
+        B.dhr_gbuffer_trace(ctx, bvh, cams[f], cams[f - 1], W, H,
+                            B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao, ao_radius=pr.ao_radius,
+                                           n_shadow=pr.n_shadow, lights=lights),
+                            g["pos"], g["nz"], g["dz"], g["mv"], ao, sh)
+    B.dhr_set_trace_counters(ctx, None)
+    cnt = [int(v) / steps for v in c.cpu().tolist()]
+    flops = cnt[1] * FLOPS_PER_NODE + cnt[3] * FLOPS_PER_TRI
+    ach = flops / (t_f / 1e3) / 1e12
     return {"workload": f"{name}: {W}x{H}, {pr.scene} scene ({scene.n_tris} tris), {pr.n_ao} AO + {pr.n_shadow} "
                         f"shadow rays/px, {pr.levels}-level SVGF", "steps": steps,
             "pass_ms": {"frame": t_f, "svgf": t_s, "gbuf": t_g, "trace": t_t},
             "trace_mrays_s": rays / (t_t / 1e3) / 1e6, "svgf_mpix_s": HW / (t_s / 1e3) / 1e6,
             "step_mrays_s": rays / ((t_f + t_s) / 1e3) / 1e6,
+            "roofline_frame": {"bound": "alu", "unit": "TFLOP/s", "peak": VALU_PEAK_TFLOPS, "achieved": ach,
+                               "frac": ach / VALU_PEAK_TFLOPS, "traced_rays": cnt[0], "node_visits": cnt[1],
+                               "tri_tests": cnt[3]},
             "roofline_svgf": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
                               "achieved": svgf_bytes_per_px(pr.levels) * HW / (t_s / 1e3) / 1e9,
                               "frac": svgf_bytes_per_px(pr.levels) * HW / (t_s / 1e3) / 1e9 / HBM_PEAK_GBS}}
@@ -646,9 +662,18 @@ def bench_backward(B, ctx, n_frames):
     fw = sum(t[0] for t in times) / len(times)
     bw = sum(t[1] for t in times) / len(times)
     px = n_frames * HW
+    # algorithmic bytes per pixel and level: the forward level reads (c, var),
+    # nz, dz and writes (c, var) (40 B); its adjoint reads the saved (c, var),
+    # nz, dz and the output's gradient and writes the input's gradient (48 B)
+    fb = px * L * 40
+    bb = px * L * 48
+    rf = lambda nb, ms: {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "achieved": nb / (ms / 1e3) / 1e9,
+                         "frac": nb / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                         "note": "VALU-bound: every tap's weight and its derivatives are recomputed"}
     return {"workload": f"{n_frames} x {W}x{H} room frames, 5 levels, MSE vs 256-spp AO",
             "forward_ms": fw, "backward_ms": bw, "fwd_bwd_ms": fw + bw,
             "fwd_bwd_mpix_s": px / ((fw + bw) / 1e3) / 1e6, "mse": loss0,
+            "roofline_forward": rf(fb, fw), "roofline_backward": rf(bb, bw),
             "grad_sigma": gs.cpu().tolist()}
 
 
