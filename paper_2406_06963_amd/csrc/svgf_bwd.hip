@@ -370,7 +370,14 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_a_rows(const BwdBatch Bt, 
                 const int e = c + b * CW + s * a;
                 const float4 nq = s_nz[e];
                 const float2 c2 = s_cv[e];
-                const float w = fused_weight(depth_coef(dzp, a, b, s, sz, eps_zp), ke, n4.w, cvp.x, np, sn, nq, c2.x);
+                // fused_weight / depth_coef written out (the same bits as in
+                // sweep 1), its reciprocal and normal term reused below
+                const float S = fabsf((float)s * ((float)a * dzp.x + (float)b * dzp.y));
+                const float iF = hw_rcp(fmaf(sz, S, eps_zp));
+                const float xn = fminf(dot3(np, f3(nq)), 1.0f);
+                const float lx = hw_log2(xn);
+                const float ew = fmaf(kNegLog2e * iF, fabsf(n4.w - nq.w), fmaf(ke, fabsf(cvp.x - c2.x), sn * lx));
+                const float w = xn > 0.0f ? hw_exp2(ew) : 0.0f;
                 const float h = b3(a) * b3(b);
                 const float wbar = h * (A * (c2.x - cpr) - K2) + 2.0f * Bc * h * h * w * c2.y;
                 const float dc = cvp.x - c2.x;
@@ -378,11 +385,8 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_a_rows(const BwdBatch Bt, 
                 cbar_c -= ww * sgn(dc) * iE;
                 gbar = fmaf(ww * fabsf(dc), sl * iE2, gbar);
                 s_l = fmaf(ww * fabsf(dc), g * iE2, s_l);
-                const float S = fabsf((float)s * ((float)a * dzp.x + (float)b * dzp.y));
-                const float iF = hw_rcp(fmaf(sz, S, eps_zp));
                 s_z = fmaf(ww * fabsf(n4.w - nq.w), S * iF * iF, s_z);
-                const float xn = fminf(dot3(np, f3(nq)), 1.0f);
-                if (w > 0.0f && xn > 0.0f) s_n = fmaf(ww, hw_log2(xn) * 0.6931471805599453f, s_n);
+                if (w > 0.0f && xn > 0.0f) s_n = fmaf(ww, lx * 0.6931471805599453f, s_n);
             }
             const float Gb = g > 0.0f ? gbar / (2.0f * g) / sk : 0.0f;
             D.coef[i] = make_float4(A, Bc, cpr, iE);
