@@ -50,3 +50,16 @@ def test_host_only_calls():
             B.dhr_create(0)
         except B.DhrError as e:
             assert e.status in (3, 4)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark measures one GPU; asked for more it says so and exits
+    # before touching a device
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
