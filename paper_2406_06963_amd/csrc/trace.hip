@@ -17,7 +17,11 @@
 namespace dhr {
 namespace {
 
-constexpr int kTileW = 16, kTileH = 8, kBlock = 128;
+// waves per workgroup; a workgroup covers an 8 kWaves x 8 pixel tile, one 8 x 8
+// square per wave (each wave's rays come from its own square, so the waves of
+// a workgroup exchange nothing; one and four waves measured slower than two
+// on the 1080p terrain)
+constexpr int kWaves = 2, kTileW = 8 * kWaves, kTileH = 8, kBlock = 64 * kWaves;
 
 struct LightD {
     uint32_t kind;
@@ -168,12 +172,13 @@ __device__ __forceinline__ void trace_block(const TraceDesc& D, uint32_t t, uint
         }
         for (uint32_t it = 0; it < nr; ++it) {
             // P == 1: ray `it` of the lane's own pixel.  P > 1: step it of the
-            // stream covers block b = 2 (it % P) + w of the 16 x 8 tile (8 x 8/P
-            // pixels), P rays of each pixel, counted in LDS.
+            // stream covers block b = kWaves (it % P) + w of the tile (8 x 8/P
+            // pixels of the wave's own square), P rays of each pixel, counted
+            // in LDS.
             uint32_t src = threadIdx.x, s = it, px = x, py = y;
             if (P > 1) {
-                const uint32_t b = 2 * (it % P) + w, q = lane / P;
-                const uint32_t lx = (b & 1) * 8 + q % 8, ly = (b >> 1) * (8 / P) + q / 8;
+                const uint32_t b = kWaves * (it % P) + w, q = lane / P;
+                const uint32_t lx = (b % kWaves) * 8 + q % 8, ly = (b / kWaves) * (8 / P) + q / 8;
                 src = (lx / 8) * 64 + ly * 8 + lx % 8;
                 s = (it / P) * P + lane % P;
                 px = tx0 + lx;
