@@ -80,6 +80,27 @@ def test_filter_parity_teacher_forced(B, ctx, preset, n, light):
     print(f"{preset}{' light' if light else ''}: max |out - oracle| over {n} frames = {worst:.2e}", flush=True)
 
 
+@pytest.mark.parametrize("preset,kw", [("tiny", dict(fallback_radius=1, var_min_history=6, alpha=0.1)),
+                                       ("ragged", dict(fallback_radius=2, var_min_history=2, alpha_moments=0.3))])
+def test_filter_parity_other_variance_params(B, ctx, preset, kw):
+    # the variance fallback's window and the history threshold that selects it,
+    # away from their defaults (teacher forcing as above)
+    pr, fr = frames(preset, 6)
+    P, Po = B.svgf_params(**kw), orc.svgf_params(**kw)
+    hist_in = None
+    worst = 0.0
+    for k, f in enumerate(fr):
+        prev = fr[k - 1] if k > 0 else None
+        ref = orc_filter(Po, pr, f, prev, hist_in)
+        hist, out, _ = gpu_filter(B, ctx, P, pr, f, prev, hist_in)
+        worst = max(worst, float(np.abs(out - ref["out"]).max()))
+        assert np.array_equal(hist[:, 3], ref["hist_out"][:, 3].astype(np.float32)), k
+        assert np.abs(hist[:, :3] - ref["hist_out"][:, :3]).max() <= ATOL, k
+        hist_in = ref["hist_out"].astype(np.float32)
+    print(f"{preset} {kw}: max |out - oracle| over 6 frames = {worst:.2e}", flush=True)
+    assert worst <= ATOL
+
+
 def test_filter_free_running(B, ctx):
     pr, fr = frames("tiny", 8)
     P, Po = B.svgf_params(), orc.svgf_params()

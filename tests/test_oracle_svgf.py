@@ -317,6 +317,44 @@ def test_fallback_variance_is_pooled_moment_variance(orc):
     np.testing.assert_array_equal(cv[valid.ravel(), 0], m1[valid.ravel()])
 
 
+def test_variance_mixed_history_radius_and_depth_edge(orc):
+    # pixels with >= 4 frames of history take max(0, mu2 - mu1^2) of their own
+    # moments (clamped when rounding made it negative); the others pool the
+    # moments of every valid neighbour in the (2R+1)^2 window whose depth
+    # matches (with dz = 0 the depth weight is 1 on the same depth and 0 across
+    # an edge of 10 units): law of total variance over that set
+    W, H = 14, 9
+    pos, nz = _plane_frame(W, H, z=2.0)
+    nz.reshape(H, W, 4)[:, 9:, 3] = 12.0                   # a depth edge at x = 9
+    dz = np.zeros((W * H, 2), np.float32)
+    rng = np.random.default_rng(21)
+    m1 = rng.random(W * H)
+    m2 = m1 ** 2 + rng.uniform(0, 0.05, W * H)
+    hl = np.where(rng.random(W * H) < 0.5, 2.0, 6.0)
+    neg = (hl >= 4) & (rng.random(W * H) < 0.2)
+    m2[neg] = m1[neg] ** 2 - 1e-3                           # rounding below mu1^2: clamped to 0
+    hist = np.column_stack([m1, m1, m2, hl])
+    valid = np.ones((H, W), bool)
+    valid[3, 4] = valid[6, 10] = False
+    nz[~valid.ravel()] = 0.0
+    Z = nz[:, 3].reshape(H, W)
+    M1, M2, HL = m1.reshape(H, W), m2.reshape(H, W), hl.reshape(H, W)
+    for R in (1, 3):
+        cv = orc.svgf_variance(orc.svgf_params(fallback_radius=R), W, H, hist, nz, dz)
+        for y in range(H):
+            for x in range(W):
+                if not valid[y, x]:
+                    continue
+                got = cv[y * W + x, 1]
+                if HL[y, x] >= 4:
+                    assert got == max(0.0, M2[y, x] - M1[y, x] ** 2)
+                    continue
+                sl = (slice(max(y - R, 0), y + R + 1), slice(max(x - R, 0), x + R + 1))
+                msk = valid[sl] & (Z[sl] == Z[y, x])
+                ref = M2[sl][msk].mean() - M1[sl][msk].mean() ** 2
+                assert abs(got - ref) < 1e-12, (R, x, y, got, ref)
+
+
 # ------------------------------------------------------------------ adjoint pins
 
 def _vjp_case(W, H, L, seed):
