@@ -6,6 +6,8 @@
   the fused G-buffer + visibility call equal to the two separate calls.
 * A 1 x 1 frame: the texel's object id against the oracle's, and the fused
   call equal to the two separate calls.
+* Non-default client id (the generator's key), AO sample offset (its
+  counter) and absolute origin offset: per-ray bits against the oracle's.
 """
 import numpy as np
 import pytest
@@ -109,3 +111,34 @@ def test_one_pixel_frame(B, ctx):
     assert int(a1[0]) <= 4 and int(s1[0, 0]) <= 2
     pos, nz, dz, mv = orc.gbuffer(so, cams[1], cams[0], 1, 1)
     assert g1["pos"].cpu().numpy()[0, 3].view(np.uint32) == orc.id_bits(pos)[0]
+
+
+@pytest.mark.parametrize("kw", [dict(client_id=7, ao_sample_offset=100, seed=12345),
+                                dict(client_id=65535, eps_origin_abs=1e-3, seed=3),
+                                dict(ao_sample_offset=65530, seed=9)])
+def test_rng_key_counter_and_origin_parameters(B, ctx, kw):
+    # the client id keys the generator, the sample offset moves the AO counter,
+    # eps_origin_abs replaces the relative origin offset: per-ray bits against
+    # the oracle's
+    import torch
+    pr, fr = frames("tiny", 2)
+    sc, so = scene(pr.scene)
+    bvh = B.dhr_build_bvh(ctx, sc.tris, sc.obj_id)
+    f = fr[1]
+    args = dict(f["trace_kw"], n_ao=6, n_shadow=3, **kw)
+    W, H, L = pr.W, pr.H, len(args["lights"])
+    HW = W * H
+    ao, sh = _counts(B, L, HW)
+    rb = torch.empty(1 + L, HW, dtype=torch.int64, device="cuda")
+    B.dhr_trace_visibility(ctx, bvh, B.trace_params(W, H, **args), dev(f["pos"]), dev(f["nz"]), ao, sh, rb)
+    _, _, bits_o = orc.trace(so, orc.trace_params(W, H, **args), f["pos"], f["nz"], ray_bits=True)
+    bits = rb.cpu().numpy().view(np.uint64)
+    rays = int((f["nz"][:, 3] > 0).sum()) * (6 + L * 3)
+    bad = popcount64(bits ^ bits_o)
+    print(f"{kw}: {bad} of {rays} rays differ", flush=True)
+    assert bad <= max(1, 1e-4 * rays)
+    # and the parameters matter: the default key and counter give other rays
+    rb0 = torch.empty_like(rb)
+    B.dhr_trace_visibility(ctx, bvh, B.trace_params(W, H, **dict(f["trace_kw"], n_ao=6, n_shadow=3)),
+                           dev(f["pos"]), dev(f["nz"]), ao, sh, rb0)
+    assert not torch.equal(rb, rb0)
