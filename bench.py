@@ -135,15 +135,13 @@ def main():
     info = bvh.info()
     P = B.svgf_params(levels=pr.levels, alpha=pr.alpha)
 
-    # three G-buffer / count slots: frame f+1 is written while frame f's
-    # filter reads frames f and f - 1
-    gb = [B.gbuffer_tensors(W, H, dev) for _ in range(3)]
-    hist = [torch.empty(HW, 4, device=dev) for _ in range(2)]
-    aos = [torch.empty(HW, dtype=torch.uint8, device=dev) for _ in range(3)]
-    shs = [torch.empty(len(lights), HW, dtype=torch.uint8, device=dev) for _ in range(3)]
-    ao, sh = aos[0], shs[0]          # the single-frame runs below
-    out = torch.empty(HW, device=dev)
-    work = torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device=dev)
+    from paper_2406_06963_amd.pipeline import FramePipeline
+
+    # frame f + 1's G-buffer + visibility launch overlaps frame f's filter on a
+    # second stream, as a renderer (or the serving loop) runs them
+    pipe = FramePipeline(ctx, bvh, W, H, pr.n_ao, len(lights), P, dev)
+    gb, hist, out, work = pipe.gb, pipe.hist, pipe.out, pipe.work
+    ao, sh = pipe.aos[0], pipe.shs[0]          # the single-frame runs below
 
     # one event pair per pass and timed step, each on the stream its kernels run on
     ev = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -154,57 +152,12 @@ def main():
                               n_shadow=pr.n_shadow, lights=lights)
 
     tps = [tparams(f) for f in range(nfr)]
+    w0, w1 = args.warmup, args.warmup + args.steps
 
-    def launch_frame(f, s):
-        # G-buffer and visibility of frame f in one launch
-        g = gb[f % 3]
-        B.dhr_gbuffer_trace(ctx, bvh, cams[f], cams[f - 1] if f > 0 else None, W, H, tps[f],
-                            g["pos"], g["nz"], g["dz"], g["mv"], aos[f % 3], shs[f % 3], stream=s)
-
-    def launch_filter(f, s):
-        g, p = gb[f % 3], gb[(f - 1) % 3]
-        fr = B.svgf_frame(W, H, pr.n_ao, aos[f % 3], g["pos"], g["nz"], g["dz"], g["mv"],
-                          p["pos"] if f > 0 else None, p["nz"] if f > 0 else None,
-                          hist[(f + 1) % 2] if f > 0 else None, hist[f % 2], out, B.pix_angle(cams[f], H), work=work)
-        B.dhr_svgf_filter(ctx, P, [fr], stream=s)
-
-    # default-priority streams: frame f + 1's G-buffer + visibility launch
-    # overlaps frame f's filter, as a renderer (or the serving loop) runs them
-    s_frame, s_filt = torch.cuda.Stream(), torch.cuda.Stream()
-
-    def run(n0, n1, timed=False):
-        rec = (lambda k, f, e, s: ev[k][f - n0][e].record(s)) if timed else (lambda k, f, e, s: None)
-        s_frame.wait_stream(torch.cuda.current_stream())
-        s_filt.wait_stream(torch.cuda.current_stream())
-        done = {}
-
-        def frame(f):
-            rec("frame", f, 0, s_frame)
-            launch_frame(f, s_frame)
-            rec("frame", f, 1, s_frame)
-
-        frame(n0)
-        for f in range(n0, n1):
-            ready = torch.cuda.Event()
-            ready.record(s_frame)
-            s_filt.wait_event(ready)                 # filter f after frame f
-            rec("svgf", f, 0, s_filt)
-            launch_filter(f, s_filt)
-            rec("svgf", f, 1, s_filt)
-            if f + 1 < n1:
-                if f > n0:
-                    s_frame.wait_event(done[f - 1])  # slot (f + 1) % 3 is filter f - 1's previous frame
-                frame(f + 1)
-            d = torch.cuda.Event()
-            d.record(s_filt)
-            done[f] = d
-        torch.cuda.current_stream().wait_stream(s_frame)
-        torch.cuda.current_stream().wait_stream(s_filt)
-
-    run(0, args.warmup)
+    pipe.run(cams, tps, 0, w0)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    run(args.warmup, args.warmup + args.steps, timed=True)
+    pipe.run(cams, tps, w0, w1, events={"frame": ev["frame"], "svgf": ev["svgf"]})
     torch.cuda.synchronize()
     t_end = time.perf_counter()
     ms_per_step = (t_end - t_start) * 1e3 / args.steps
@@ -213,19 +166,10 @@ def main():
     # history (the per-pass times without overlap), then as two launches
     # (dhr_gbuffer, then dhr_trace_visibility): the per-pass breakdown and the
     # visibility kernel's own roofline
-    cs = torch.cuda.current_stream()
-    for f in range(args.warmup):
-        launch_frame(f, cs)
-        launch_filter(f, cs)
+    pipe.run(cams, tps, 0, w0, overlap=False)
     torch.cuda.synchronize()
     t_seq = time.perf_counter()
-    for k, f in enumerate(range(args.warmup, args.warmup + args.steps)):
-        ev["frame_seq"][k][0].record()
-        launch_frame(f, cs)
-        ev["frame_seq"][k][1].record()
-        ev["svgf_seq"][k][0].record()
-        launch_filter(f, cs)
-        ev["svgf_seq"][k][1].record()
+    pipe.run(cams, tps, w0, w1, overlap=False, events={"frame": ev["frame_seq"], "svgf": ev["svgf_seq"]})
     torch.cuda.synchronize()
     ms_per_step_seq = (time.perf_counter() - t_seq) * 1e3 / args.steps
     for k, f in enumerate(range(args.warmup, args.warmup + args.steps)):
