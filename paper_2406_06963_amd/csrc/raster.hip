@@ -44,7 +44,6 @@ constexpr uint32_t kMidArea = 64;      // pixel centres a thread of the medium p
 constexpr int kBlockPx = 64;           // side of a large triangle's block
 constexpr float kMargin = 0.5f;        // pixels
 constexpr float kEdgeRange = 1.0e5f;   // projected coordinates for which edges are used
-constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 struct RasterDesc {
     const float4* tris;

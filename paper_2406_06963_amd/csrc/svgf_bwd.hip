@@ -194,7 +194,6 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_b_direct(const BwdBatch Bt
     }
     const float2* cv = D.save + (size_t)level * W * H;
     const float2 cvq = cv[i];
-    const float3 nq = f3(n4);
     const float sz = P.sz[level], sn = P.sn[level];
     float acc_c = D.aux[i].y, acc_v = 0.0f;
 #pragma unroll
