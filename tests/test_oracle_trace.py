@@ -16,6 +16,7 @@
   computed by quadrature.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -162,7 +163,16 @@ def _fig1_scene(cone_deg):
     return np.array(tris, np.float32), lights
 
 
+def _fig1_golden():
+    """The bitmasks Fig. 1 prints, from tests/golden/fig1_bitmasks.txt."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "fig1_bitmasks.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    return {case: int(bits, 2) for case, bits in rows}
+
+
 def test_fig1_bitmask_example(orc):
+    golden = _fig1_golden()
+    assert set(golden) == {"hard", "soft"}
     tris, hard = _fig1_scene(0.0)
     s = orc.Scene(tris)
     pos = np.array([[0.0, 0.0, 0.0, 0.0]], np.float32)
@@ -173,11 +183,12 @@ def test_fig1_bitmask_example(orc):
         _, sh, _ = orc.trace(s, P, pos, nz)
         return sum(int(sh[i, 0]) << i for i in range(3))
 
-    assert all(mask(hard, f) == 0b110 for f in range(16))
+    assert all(mask(hard, f) == golden["hard"] for f in range(16))
     _, soft = _fig1_scene(10.0)
     masks = [mask(soft, f) for f in range(64)]
     # lights 0 and 1 never change; light 2 is sometimes revealed as occluded
-    assert set(masks) == {0b110, 0b010}
+    # (the rays that miss the occluder keep the hard-shadow mask)
+    assert set(masks) == {golden["hard"], golden["soft"]}
 
 
 def test_penumbra_matches_quadrature(orc):
