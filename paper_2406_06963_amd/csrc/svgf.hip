@@ -128,6 +128,9 @@ __global__ __launch_bounds__(kSvgfBlock) void temporal_kernel(const SvgfBatch B,
 // LDS for the spatial fallback.
 constexpr int kVarRim = 3;
 
+// R = fallback radius (0..3): the (2R + 1)^2 taps are unrolled, so their LDS
+// reads and weights overlap instead of waiting tap by tap.
+template <int R>
 __global__ __launch_bounds__(kSvgfBlock) void variance_kernel(const SvgfBatch B, const SvgfK P) {
     constexpr int TW = kSvgfTile + 2 * kVarRim;
     __shared__ float4 s_nz[TW * TW];  // zero for invalid or outside pixels
@@ -173,21 +176,30 @@ __global__ __launch_bounds__(kSvgfBlock) void variance_kernel(const SvgfBatch B,
     {
         // pooled moments of the valid neighbours, depth/normal weights of level 0;
         // one pass with FP64 sums: var = sum w (mu2 - mu1^2) / sum w + (sum w mu1^2 / sum w - mbar^2)
-        const int R = (int)P.R;
         const float2 dzp = D.dz[i];
         const float3 np = f3(n4);
         const float eps_zp = P.eps_z * n4.w;
         const int c = (int)(threadIdx.x / kSvgfTile + kVarRim) * TW + (int)(threadIdx.x % kSvgfTile) + kVarRim;
+        // kz of the taps after the centre in raster order; a tap and its
+        // mirror (-a, -b) have the same |a dz/dx + b dz/dy|, hence the same kz
+        constexpr int K = 2 * R + 1, centre = (K * K - 1) / 2;
+        float kzh[centre > 0 ? centre : 1];
+#pragma unroll
+        for (int t = 0; t < centre; ++t)
+            kzh[t] = depth_coef(dzp, (centre + 1 + t) % K - R, (centre + 1 + t) / K - R, 1, P.sz[0], eps_zp);
         double sw = 0.0, s1 = 0.0, s11 = 0.0, s2 = 0.0;
+#pragma unroll
         for (int b = -R; b <= R; ++b) {
+#pragma unroll
             for (int a = -R; a <= R; ++a) {
+                const int idx = (b + R) * K + a + R;
                 const int e = c + b * TW + a;
-                const float4 nq = s_nz[e];
-                if (!(nq.w > 0.0f)) continue;
-                double w = 1.0;
-                if (a != 0 || b != 0)
-                    w = (double)fused_weight(depth_coef(dzp, a, b, 1, P.sz[0], eps_zp), 0.0f, n4.w, 0.0f, np, P.sn[0],
-                                             nq, 0.0f);
+                // an invalid or outside neighbour was staged with a zero
+                // normal: its weight is exactly 0 and the sums stay unchanged
+                const double w = idx == centre
+                                     ? 1.0
+                                     : (double)fused_weight(idx > centre ? kzh[idx - centre - 1] : kzh[centre - 1 - idx],
+                                                            0.0f, n4.w, 0.0f, np, P.sn[0], s_nz[e], 0.0f);
                 const double m1 = (double)s_m[e].x;
                 sw += w;
                 s1 = fma(w, m1, s1);
@@ -722,7 +734,12 @@ dhr_status dhr_svgf_filter(dhr_ctx* ctx, const dhr_svgf_params* params, const dh
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     st = for_chunks(ctx, descs, "dhr_svgf_filter", K.levels, s, K, [&](const SvgfBatch& B, dim3 grid) {
         hipLaunchKernelGGL(temporal_kernel, grid, dim3(kSvgfBlock), 0, s, B, K);
-        hipLaunchKernelGGL(variance_kernel, grid, dim3(kSvgfBlock), 0, s, B, K);
+        switch (K.R) {
+            case 0: hipLaunchKernelGGL(variance_kernel<0>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+            case 1: hipLaunchKernelGGL(variance_kernel<1>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+            case 2: hipLaunchKernelGGL(variance_kernel<2>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+            default: hipLaunchKernelGGL(variance_kernel<3>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
+        }
     });
     return st;
 }

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_a_direct(const BwdBatch Bt
                 cbar_c -= ww * sgn(dc) * iE;
                 gbar = fmaf(ww * fabsf(dc), sl * iE2, gbar);
                 s_l = fmaf(ww * fabsf(dc), g * iE2, s_l);
-                const float S = fabsf((float)s * ((float)a * dzp.x + (float)b * dzp.y));
+                const float S = tap_span(dzp, a, b, s);
                 const float iF = hw_rcp(fmaf(sz, S, eps_zp));
                 s_z = fmaf(ww * fabsf(n4.w - nq.w), S * iF * iF, s_z);
                 const float xn = fminf(dot3(np, f3(nq)), 1.0f);
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_a_rows(const BwdBatch Bt, 
                 const float2 c2 = s_cv[e];
                 // fused_weight / depth_coef written out (the same bits as in
                 // sweep 1), its reciprocal and normal term reused below
-                const float S = fabsf((float)s * ((float)a * dzp.x + (float)b * dzp.y));
+                const float S = tap_span(dzp, a, b, s);
                 const float iF = hw_rcp(fmaf(sz, S, eps_zp));
                 const float xn = fminf(dot3(np, f3(nq)), 1.0f);
                 const float lx = hw_log2(xn);

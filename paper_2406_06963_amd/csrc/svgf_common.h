@@ -157,10 +157,20 @@ __device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2
 __device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// |s (a dz/dx + b dz/dy)|, the depth change the gradient predicts at tap
+// (a, b) of stride s, rounded as b dz/dy, then one fma: with contraction off
+// the compiler cannot fuse the other product instead once a and b are
+// constants (it would for |a| = 1, |b| = 3), so unrolled and looped code give
+// the same bits.  The sum can nearly cancel at grazing angles, where an ulp of
+// it moves the weight; the mirror (-a, -b) gives the same bits.
+__device__ __forceinline__ float tap_span(float2 dzp, int a, int b, int s) {
+#pragma clang fp contract(off)
+    return fabsf((float)s * fmaf((float)a, dzp.x, (float)b * dzp.y));
+}
+
 // kz of the tap pair (a, b) / (-a, -b) at stride s
 __device__ __forceinline__ float depth_coef(float2 dzp, int a, int b, int s, float sz, float eps_zp) {
-    const float S = fabsf((float)s * ((float)a * dzp.x + (float)b * dzp.y));
-    return kNegLog2e * hw_rcp(fmaf(sz, S, eps_zp));
+    return kNegLog2e * hw_rcp(fmaf(sz, tap_span(dzp, a, b, s), eps_zp));
 }
 
 __device__ __forceinline__ float fused_weight(float kz, float ke, float zp, float cp, float3 np, float sn, float4 nq,
