@@ -33,7 +33,7 @@ def _bits(t):
     return t.view(torch.int32) if t.dtype == torch.float32 else t
 
 
-@pytest.mark.parametrize("preset", ["tiny", "ragged", "room720"])
+@pytest.mark.parametrize("preset", ["tiny", "ragged", "room720", "terrain1080"])
 def test_overlapped_frames_equal_one_at_a_time(B, ctx, preset):
     import torch
     from paper_2406_06963_amd.pipeline import FramePipeline

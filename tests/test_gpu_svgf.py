@@ -81,10 +81,12 @@ def test_filter_parity_teacher_forced(B, ctx, preset, n, light):
 
 
 @pytest.mark.parametrize("preset,kw", [("tiny", dict(fallback_radius=1, var_min_history=6, alpha=0.1)),
-                                       ("ragged", dict(fallback_radius=2, var_min_history=2, alpha_moments=0.3))])
+                                       ("ragged", dict(fallback_radius=2, var_min_history=2, alpha_moments=0.3)),
+                                       ("ragged", dict(fallback_radius=0, var_min_history=5))])
 def test_filter_parity_other_variance_params(B, ctx, preset, kw):
-    # the variance fallback's window and the history threshold that selects it,
-    # away from their defaults (teacher forcing as above)
+    # the variance fallback's window (each radius 0-3 has its own kernel; 3 is
+    # the default of the other tests) and the history threshold that selects
+    # it, away from their defaults (teacher forcing as above)
     pr, fr = frames(preset, 6)
     P, Po = B.svgf_params(**kw), orc.svgf_params(**kw)
     hist_in = None
