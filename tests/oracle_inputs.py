@@ -25,12 +25,23 @@ def pix_of(cam, H):
     return np.float32(2.0 * math.tan(0.5 * cam.fov_y) / H)
 
 
+def frames(preset, n: int, n_ao: int | None = None, n_shadow: int | None = None, cams=None):
+    """(preset, [dict(pos, nz, dz, mv, ao, sh, cam, pix, params)]) for frames 0..n-1
+    of a preset given by name (cached) or as a workloads.Preset; `cams`
+    replaces the preset's camera path."""
+    if isinstance(preset, str) and cams is None:
+        return _frames_named(preset, n, n_ao, n_shadow)
+    return _frames(wl.preset(preset) if isinstance(preset, str) else preset, n, n_ao, n_shadow, cams)
+
+
 @functools.lru_cache(maxsize=None)
-def frames(preset_name: str, n: int, n_ao: int | None = None, n_shadow: int | None = None):
-    """(preset, [dict(pos, nz, dz, mv, ao, sh, cam, pix, params)]) for frames 0..n-1."""
-    pr = wl.preset(preset_name)
+def _frames_named(name: str, n: int, n_ao, n_shadow):
+    return _frames(wl.preset(name), n, n_ao, n_shadow)
+
+
+def _frames(pr, n: int, n_ao, n_shadow, cams=None):
     sc, so = scene(pr.scene)
-    cams = wl.camera_path(pr.camera, n, sc)
+    cams = wl.camera_path(pr.camera, n, sc) if cams is None else cams
     lights = wl.lights_for(pr.scene)
     nao = pr.n_ao if n_ao is None else n_ao
     nsh = pr.n_shadow if n_shadow is None else n_shadow
