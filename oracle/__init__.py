@@ -16,7 +16,9 @@ Parity status of each function (pins live in ``tests/test_oracle_*.py``):
   gbuffer            pinned: closed-form plane depth/normal/motion/dz
   trace              pinned: lone plane, plane+wall closed form, penumbra
                      quadrature, radius monotonicity, bitmask example
-  svgf_temporal      pinned: running mean, integer shift, disocclusion
+  svgf_temporal      pinned: running mean, integer shift, disocclusion,
+                     fractional motion over a linear history (exact blend),
+                     renormalisation over rejected taps, the h' max rule
   svgf_variance      pinned: moments identity, constant / two-level patches
   svgf_atrous        pinned: constant image, scipy normalised convolution
   svgf_spatial_vjp   pinned: dual-number JVP dot-product test, central differences

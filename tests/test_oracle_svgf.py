@@ -439,3 +439,145 @@ def test_tiny_negative_motion_uses_the_pixel_itself(orc):
     ref = orc.svgf_temporal(P, W, H, n_ao, ao, pos, nz, np.zeros_like(mv), pos, nz, hist_in, 0.001)
     np.testing.assert_array_equal(out, ref)
     assert (out[:, 3] == 4.0).all()
+
+
+# ------------------------------------------- fractional back-projection pins
+#
+# Section 3.3 back-projects each pixel with its motion vector into the
+# previous frame and blends the history found there.  The blend is bilinear
+# over the 2 x 2 pixels around the back-projected point, renormalised over
+# the taps that survive the consistency tests, and the history length of the
+# result is one more than the largest length among those taps (the reading
+# of the history-length rule recorded in the design notes).  The expected
+# values below come from facts that do not depend on how the weights are
+# coded: a bilinear blend reproduces any function that is linear in x and y
+# exactly, so over a linearly varying history the blend at p + mv is the
+# linear function at p + mv; a partial blend is written out by hand.
+
+def _linear_history(W, H):
+    """History channels linear in (x, y); lengths 2, 7, 3, 5 by pixel parity
+    (x even / odd, y even / odd), so any 2 x 2 footprint holds all four."""
+    yy, xx = np.divmod(np.arange(W * H), W)
+    c = 0.1 + 0.05 * xx + 0.02 * yy
+    m1 = 0.2 + 0.03 * xx - 0.01 * yy
+    m2 = 0.3 + 0.01 * xx + 0.04 * yy
+    hl = np.array([[2.0, 7.0], [3.0, 5.0]])[yy % 2, xx % 2]
+    return np.column_stack([c, m1, m2, hl]).astype(np.float32)
+
+
+def _lin(x, y):
+    """The three history channels at a continuous position (x, y)."""
+    return (0.1 + 0.05 * x + 0.02 * y, 0.2 + 0.03 * x - 0.01 * y, 0.3 + 0.01 * x + 0.04 * y)
+
+
+def _ema(hist_c, hist_m1, hist_m2, xs, a):
+    return hist_c + a * (xs - hist_c), hist_m1 + a * (xs - hist_m1), hist_m2 + a * (xs * xs - hist_m2)
+
+
+def _run_motion(orc, W, H, mv_xy, prev_pos=None):
+    n_ao = 4
+    pos, nz = _plane_frame(W, H)
+    hist_in = _linear_history(W, H)
+    ao = np.full(W * H, 1, np.uint8)            # x_s = 0.25 everywhere
+    mv = np.tile(np.array(mv_xy, np.float32), (W * H, 1))
+    pp = pos if prev_pos is None else prev_pos
+    out = orc.svgf_temporal(orc.svgf_params(), W, H, n_ao, ao, pos, nz, mv, pp, nz, hist_in, 0.001)
+    return out.reshape(H, W, 4), mv[0]
+
+
+def test_fractional_motion_blends_a_linear_history_exactly(orc):
+    # motion (0.25, 0.75): taps at x, x + 1 and y, y + 1 with fractions
+    # 0.25 / 0.75; every interior pixel sees history lengths {2, 7, 3, 5}
+    W, H = 8, 6
+    out, _ = _run_motion(orc, W, H, (0.25, 0.75))
+    # one pixel by hand: (2, 1) back-projects to (2.25, 1.75)
+    #   c = 0.1 + 0.05 * 2.25 + 0.02 * 1.75 = 0.2475, mu1 = 0.25, mu2 = 0.3925
+    #   h' = 1 + max(2, 7, 3, 5) = 8, a = max(0.2, 1 / 8) = 0.2
+    #   c' = 0.2475 + 0.2 * (0.25 - 0.2475) = 0.248
+    #   mu1' = 0.25, mu2' = 0.3925 + 0.2 * (0.0625 - 0.3925) = 0.3265
+    np.testing.assert_allclose(out[1, 2], [0.248, 0.25, 0.3265, 8.0], rtol=0, atol=1e-6)
+    # every pixel whose four taps lie inside the image
+    for y in range(H - 1):
+        for x in range(W - 1):
+            ref = _ema(*_lin(x + 0.25, y + 0.75), 0.25, 0.2)
+            np.testing.assert_allclose(out[y, x, :3], ref, rtol=0, atol=1e-6, err_msg=f"{(x, y)}")
+            assert out[y, x, 3] == 8.0, (x, y)
+
+
+def test_fractional_negative_motion_and_the_image_border(orc):
+    # motion (-0.6, 0.3) in fp32: floor (-1, 0), fractions (0.4, 0.3)
+    W, H = 8, 6
+    out, mv = _run_motion(orc, W, H, (-0.6, 0.3))
+    mx, my = float(mv[0]), float(mv[1])
+    for y in range(H - 1):
+        for x in range(1, W):
+            ref = _ema(*_lin(x + mx, y + my), 0.25, 0.2)
+            np.testing.assert_allclose(out[y, x, :3], ref, rtol=0, atol=1e-6, err_msg=f"{(x, y)}")
+            assert out[y, x, 3] == 8.0, (x, y)
+    # column 0: the taps at x = -1 are outside, the two at x = 0 remain with
+    # weights 0.4 * 0.7 and 0.4 * 0.3, renormalised by their sum 0.4: a linear
+    # blend along y only.  Their lengths are 2 and 3 (x even), so h' = 4 and
+    # the ramp gives a = max(0.2, 1 / 4) = 0.25.
+    for y in range(H - 1):
+        hl = 1.0 + max(2.0 if y % 2 == 0 else 3.0, 3.0 if y % 2 == 0 else 2.0)
+        assert hl == 4.0
+        ref = _ema(*_lin(0.0, y + my), 0.25, 0.25)
+        np.testing.assert_allclose(out[y, 0, :3], ref, rtol=0, atol=1e-6, err_msg=f"{y}")
+        assert out[y, 0, 3] == 4.0
+    # by hand for (0, 2): c = 0.1 + 0.02 * 2.3 = 0.146, c' = 0.146 + 0.25 * (0.25 - 0.146) = 0.172
+    assert abs(out[2, 0, 0] - 0.172) <= 1e-6
+    # bottom row: the taps at y = H are outside, a blend along x only
+    for x in range(1, W):
+        hl = 1.0 + max(2.0, 7.0) if (H - 1) % 2 == 0 else 1.0 + max(3.0, 5.0)
+        a = max(0.2, 1.0 / hl)
+        ref = _ema(*_lin(x + mx, H - 1), 0.25, a)
+        np.testing.assert_allclose(out[H - 1, x, :3], ref, rtol=0, atol=1e-6, err_msg=f"{x}")
+        assert out[H - 1, x, 3] == hl
+
+
+def test_rejected_tap_renormalises_the_rest(orc):
+    # motion (0.25, 0.75); the history sample at (3, 2) belongs to another
+    # object, so pixel (2, 1) keeps three of its four taps
+    W, H = 8, 6
+    pos, _ = _plane_frame(W, H)
+    prev_pos = pos.copy()
+    prev_pos[2 * W + 3, 3] = np.array([9], np.uint32).view(np.float32)[0]
+    out, _ = _run_motion(orc, W, H, (0.25, 0.75), prev_pos=prev_pos)
+    # bilinear factors of (2, 1), (3, 1), (2, 2), (3, 2): 3/16, 1/16, 9/16, 3/16;
+    # without the last the weights are 3/13, 1/13, 9/13
+    c = (3 * 0.22 + 0.27 + 9 * 0.24) / 13            # c at (2,1), (3,1), (2,2)
+    m1 = (3 * 0.25 + 0.28 + 9 * 0.24) / 13
+    m2 = (3 * 0.36 + 0.37 + 9 * 0.40) / 13
+    # lengths of the surviving taps: 3, 5, 2 -> h' = 6, a = max(0.2, 1/6) = 0.2
+    np.testing.assert_allclose(out[1, 2], [c + 0.2 * (0.25 - c), m1 + 0.2 * (0.25 - m1),
+                                           m2 + 0.2 * (0.0625 - m2), 6.0], rtol=0, atol=1e-6)
+    # the rejected sample is also the (0, 0) tap of pixel (3, 2), the (1, 0)
+    # tap of (2, 2), the (0, 1) tap of (3, 1) and the (1, 1) tap of (2, 1);
+    # pixels whose footprint avoids it are unaffected
+    ref = _ema(*_lin(5 + 0.25, 3 + 0.75), 0.25, 0.2)
+    np.testing.assert_allclose(out[3, 5, :3], ref, rtol=0, atol=1e-6)
+    # (3, 2): its own sample (3/16) is rejected; (4, 2) 1/16, (3, 3) 9/16 and
+    # (4, 3) 3/16 remain -> weights 1/13, 9/13, 3/13 on c = 0.34, 0.31, 0.36;
+    # lengths 2, 5, 3 -> h' = 6
+    c = (0.34 + 9 * 0.31 + 3 * 0.36) / 13
+    np.testing.assert_allclose(out[2, 3, 0], c + 0.2 * (0.25 - c), rtol=0, atol=1e-6)
+    assert out[2, 3, 3] == 6.0
+
+
+def test_short_histories_take_the_ramp_of_the_longest_tap(orc):
+    # lengths {1, 2, 1, 3} by parity: h' = 1 + 3 = 4, so a = 1/4 > alpha;
+    # a blend of the lengths would give a non-integer h' and another a
+    W, H, n_ao = 6, 4, 4
+    pos, nz = _plane_frame(W, H)
+    hist_in = _linear_history(W, H)
+    yy, xx = np.divmod(np.arange(W * H), W)
+    hist_in[:, 3] = np.array([[1.0, 2.0], [1.0, 3.0]])[yy % 2, xx % 2]
+    ao = np.full(W * H, 3, np.uint8)            # x_s = 0.75
+    mv = np.tile(np.array([0.5, 0.25], np.float32), (W * H, 1))
+    out = orc.svgf_temporal(orc.svgf_params(), W, H, n_ao, ao, pos, nz, mv, pos, nz, hist_in, 0.001)
+    out = out.reshape(H, W, 4)
+    for y in range(H - 1):
+        for x in range(W - 1):
+            ref = _ema(*_lin(x + 0.5, y + 0.25), 0.75, 0.25)
+            np.testing.assert_allclose(out[y, x, :3], ref, rtol=0, atol=1e-6, err_msg=f"{(x, y)}")
+            assert out[y, x, 3] == 4.0
