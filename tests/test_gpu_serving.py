@@ -69,3 +69,131 @@ def test_alone_equals_mix(setup):
             assert torch.equal(o1, o2), (sp.client_id, s1)
             checked += 1
     assert checked > 8
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _oracle_client(B, ctx, scenes, spec, served, n_check):
+    """The oracle renders the first n_check served frames of one client in
+    the served order (G-buffer with the previously served camera as history
+    camera, visibility with the client's random-number key, the filter with
+    its own history).  Returns, per frame, the fraction of pixels where the
+    served output differs by more than 1e-4 from the oracle's free-running
+    output, and checks the HIP passes teacher-forced on the oracle's inputs:
+    per-ray visibility bits, and the filter fed the oracle's G-buffer, counts
+    and history (|out - oracle| <= 1e-4, identical history lengths)."""
+    import torch
+
+    import oracle as orc
+    sc = wl.make_scene(spec.scene)
+    so = orc.Scene(sc.tris, sc.obj_id)
+    lights = wl.lights_for(spec.scene)
+    r_ao = scenes[spec.scene]["ao_radius"]
+    W, H, HW = spec.W, spec.H, spec.W * spec.H
+    Pf, Po = B.svgf_params(), orc.svgf_params()
+    free, tf_err, bad_rays, rays = [], 0.0, 0, 0
+    prev_cam, prev, hist = None, None, None
+    for seq, cam, out_gpu in served[:n_check]:
+        pos, nz, dz, mv = orc.gbuffer(so, cam, prev_cam, W, H)
+        kw = dict(frame=seq, client_id=spec.client_id, seed=5, n_ao=1, ao_radius=r_ao, n_shadow=1, lights=lights)
+        ao, sh, bits_o = orc.trace(so, orc.trace_params(W, H, **kw), pos, nz, ray_bits=True)
+        pix = np.float32(2.0 * np.tan(0.5 * cam.fov_y) / H)
+        ref = orc.svgf_filter(Po, W, H, 1, ao, pos, nz, dz, mv, prev[0] if prev else None,
+                              prev[1] if prev else None, hist, pix)
+        # free-running: the served frame against the oracle's own sequence
+        free.append(float((np.abs(out_gpu - ref["out"]) > 1e-4).mean()))
+        # teacher-forced visibility on the oracle's G-buffer
+        ao_g = torch.empty(HW, dtype=torch.uint8, device="cuda")
+        sh_g = torch.empty(len(lights), HW, dtype=torch.uint8, device="cuda")
+        rb = torch.empty(1 + len(lights), HW, dtype=torch.int64, device="cuda")
+        B.dhr_trace_visibility(ctx, scenes[spec.scene]["bvh"], B.trace_params(W, H, **kw), _dev(pos), _dev(nz),
+                               ao_g, sh_g, rb)
+        bits_g = rb.cpu().numpy().view(np.uint64)
+        bad_rays += int(np.unpackbits((bits_g ^ bits_o).view(np.uint8)).sum())
+        rays += int((nz[:, 3] > 0).sum()) * (1 + len(lights))
+        # teacher-forced filter
+        hist_g = torch.empty(HW, 4, device="cuda")
+        out_g = torch.empty(HW, device="cuda")
+        work = torch.empty(B.dhr_svgf_workspace_bytes(W, H, Pf, 0) // 4, device="cuda")
+        fr = B.svgf_frame(W, H, 1, _dev(ao), _dev(pos), _dev(nz), _dev(dz), _dev(mv),
+                          _dev(prev[0]) if prev else None, _dev(prev[1]) if prev else None,
+                          _dev(hist) if hist is not None else None, hist_g, out_g, float(pix), work=work)
+        B.dhr_svgf_filter(ctx, Pf, [fr])
+        tf_err = max(tf_err, float(np.abs(out_g.cpu().numpy() - ref["out"]).max()))
+        assert np.array_equal(hist_g.cpu().numpy()[:, 3], ref["hist_out"][:, 3].astype(np.float32)), seq
+        prev_cam, prev, hist = cam, (pos, nz), ref["hist_out"].astype(np.float32)
+    return free, tf_err, bad_rays, rays
+
+
+@pytest.mark.timeout(900)
+def test_c5_shape_alone_equals_mix_and_oracle(setup):
+    """64 clients with the serving workload's resolution mix (640 x 360,
+    1280 x 720, 1920 x 1080) and scenes, Poisson 30 Hz requests delayed by
+    U[0, 200] ms, and the 200 ms staleness tolerance of Section 4.1: every
+    served frame of every client equals the same client's frames run alone
+    (bitwise); four clients' served sequences are also rendered by the oracle
+    (free-running fraction reported, teacher-forced passes within 1e-4)."""
+    import torch
+    B, ctx, scenes = setup
+    specs = sv.make_clients(64)
+    assert {(s.W, s.H) for s in specs} == set(sv.RESOLUTIONS)
+    reqs = sv.request_trace(specs, duration_s=1.0, rate_hz=30.0, max_delay_s=0.2)
+    ex = sv.GpuExecutor(ctx, scenes, n_streams=3)
+    server = sv.Server(ex, max_batch=8, max_inflight=3, keep_outputs=True, max_stale_s=0.2)
+    for sp in specs:
+        assert server.connect(sp)
+    print(f"case: 64 clients, {len(reqs)} requests over 1 s of virtual time", flush=True)
+    # virtual time in 25 ms windows: every client with a delivered request
+    # joins the window's batches, so batches mix clients, scenes and
+    # resolutions; a request waiting past 200 ms since it was sent is dropped
+    i = 0
+    for k in range(1, 50):
+        t = 0.025 * k
+        while i < len(reqs) and reqs[i].deliver_t <= t:
+            server.offer(reqs[i])
+            i += 1
+        while server.tick(t):
+            pass
+        server.drain()
+    st = server.stats.summary(1.0)
+    print("mix:", {k: v for k, v in st.items() if not k.endswith("_ms")}, flush=True)
+    assert st["mean_batch"] > 2.0 and st["dropped_stale"] > 0 and st["dropped_out_of_order"] > 0
+    assert all(server.clients[sp.client_id].served for sp in specs)
+    cams = {(r.client_id, r.seq): r.camera for r in reqs}
+    checked = 0
+    for sp in specs:
+        mine = server.clients[sp.client_id].served
+        seqs = [s for s, _ in mine]
+        alone_ex = sv.GpuExecutor(ctx, scenes, n_streams=1)
+        alone = sv.Server(alone_ex, max_batch=1, max_inflight=1, keep_outputs=True, max_stale_s=1e9)
+        alone.connect(sp)
+        for s in seqs:
+            alone.offer(sv.Request(sp.client_id, s, cams[(sp.client_id, s)], 0.0, 0.0))
+            alone.tick()
+            alone.drain()
+        a = alone.clients[sp.client_id].served
+        assert [s for s, _ in a] == seqs
+        for (s1, o1), (s2, o2) in zip(mine, a):
+            assert torch.equal(o1, o2), (sp.client_id, s1)
+            checked += 1
+        alone.disconnect(sp.client_id)
+    print(f"alone == mix for all {checked} served frames of 64 clients", flush=True)
+    # four clients against the oracle: the two smallest of each scene and
+    # the first of each larger resolution
+    pick = []
+    for key in (lambda s: s.W == 640 and s.scene == "spheres", lambda s: s.W == 640 and s.scene == "room",
+                lambda s: s.W == 1280, lambda s: s.W == 1920):
+        pick.append(next(s for s in specs if key(s)))
+    for sp in pick:
+        served = [(s, cams[(sp.client_id, s)], o.cpu().numpy()) for s, o in server.clients[sp.client_id].served]
+        n_check = 5 if sp.W < 1920 else 3
+        free, tf_err, bad, rays = _oracle_client(B, ctx, scenes, sp, served, n_check)
+        print(f"client {sp.client_id} {sp.W}x{sp.H} {sp.scene}: served seqs {[s for s, *_ in served[:n_check]]}; "
+              f"teacher-forced max |out - oracle| {tf_err:.2e}; rays differing {bad} of {rays}; "
+              f"free-running fraction beyond 1e-4 per frame {free}", flush=True)
+        assert tf_err <= 1e-4
+        assert bad <= 1e-4 * rays
+        assert max(free) <= 2e-2
