@@ -389,6 +389,23 @@ typedef struct {
 dhr_status dhr_svgf_filter(dhr_ctx* ctx, const dhr_svgf_params* params, const dhr_svgf_frame* frames,
                            uint32_t n_frames, dhr_stream stream);
 
+/* For callers that cannot allocate device memory or pass a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): dhr_svgf_filter with every frame's scratch taken from a
+ * library-owned device array of DHR_SVGF_NOALLOC_SCRATCH_BYTES bytes per GPU
+ * (allocated when the library is loaded, held until the process ends).  The
+ * frames are as for dhr_svgf_filter except that `work` must be NULL; frame k
+ * uses dhr_svgf_workspace_bytes(W,H,p,0) bytes rounded up to 256.  The call
+ * allocates nothing.  Every call on one GPU shares that GPU's array (nothing
+ * in it needs to start at zero; it keeps the last call's contents): calls
+ * that overlap on one GPU -- on different streams, or from different
+ * contexts -- race and give undefined results.  Errors: as dhr_svgf_filter,
+ * plus INVALID_ARG when work is not NULL or the frames need more than
+ * DHR_SVGF_NOALLOC_SCRATCH_BYTES (one 1920 x 1080 frame needs 41.5 MB). */
+#define DHR_SVGF_NOALLOC_SCRATCH_BYTES (64ull << 20)
+dhr_status dhr_svgf_filter_noalloc(dhr_ctx* ctx, const dhr_svgf_params* params, const dhr_svgf_frame* frames,
+                                   uint32_t n_frames, dhr_stream stream);
+
 /* Differentiable part alone: the a-trous levels applied to given (c, var). */
 typedef struct {
     uint32_t W, H;

@@ -107,7 +107,10 @@ EXPORTS = ["dhr_create", "dhr_destroy", "dhr_last_error", "dhr_sync", "dhr_versi
            "dhr_svgf_backward", "dhr_svgf_workspace_bytes", "dhr_philox4x32_10", "dhr_set_trace_counters",
            "dhr_encode_frame", "dhr_build_bvh_device", "dhr_refit_bvh", "dhr_bvh_export",
            "dhr_gbuffer_raster_workspace_bytes", "dhr_gbuffer_raster", "dhr_build_bvh_instanced",
-           "dhr_gbuffer_trace", "dhr_gbuffer_trace_batch"]
+           "dhr_gbuffer_trace", "dhr_gbuffer_trace_batch", "dhr_svgf_filter_noalloc"]
+
+# bytes of the library-owned scratch of dhr_svgf_filter_noalloc (per GPU)
+SVGF_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _lib = None
 
@@ -145,6 +148,7 @@ def load(path: str = LIB_PATH):
     L.dhr_svgf_default_params.argtypes = [C.POINTER(dhr_svgf_params)]
     L.dhr_svgf_default_params.restype = None
     L.dhr_svgf_filter.argtypes = [vp, C.POINTER(dhr_svgf_params), C.POINTER(dhr_svgf_frame), u32, vp]
+    L.dhr_svgf_filter_noalloc.argtypes = [vp, C.POINTER(dhr_svgf_params), C.POINTER(dhr_svgf_frame), u32, vp]
     L.dhr_svgf_spatial_forward.argtypes = [vp, C.POINTER(dhr_svgf_params), C.POINTER(dhr_svgf_spatial_frame), u32, vp]
     L.dhr_svgf_backward.argtypes = [vp, C.POINTER(dhr_svgf_params), C.POINTER(dhr_svgf_bwd_frame), u32, vp, vp]
     L.dhr_svgf_workspace_bytes.argtypes = [u32, u32, C.POINTER(dhr_svgf_params), i32]
@@ -431,6 +435,13 @@ def dhr_svgf_filter(ctx, params, frames, stream=None):
     arr = (dhr_svgf_frame * max(len(frames), 1))(*frames)
     _check(ctx, load().dhr_svgf_filter(ctx.handle, C.byref(params), arr, len(frames), _stream(stream)),
            "dhr_svgf_filter")
+
+
+def dhr_svgf_filter_noalloc(ctx, params, frames, stream=None):
+    """dhr_svgf_filter with the library's own scratch (frames without work)."""
+    arr = (dhr_svgf_frame * max(len(frames), 1))(*frames)
+    _check(ctx, load().dhr_svgf_filter_noalloc(ctx.handle, C.byref(params), arr, len(frames), _stream(stream)),
+           "dhr_svgf_filter_noalloc")
 
 
 def spatial_frame(W, H, cv_in, nz, dz, out, save=None, work=None) -> dhr_svgf_spatial_frame:

@@ -42,6 +42,12 @@ dhr_status dhr_create(int device, dhr_ctx** out) {
     dhr_ctx* c = new dhr_ctx;
     c->device = device;
     c->n_cu = prop.multiProcessorCount;
+    const dhr_status st = dhr::svgf_scratch_init(c);
+    if (st != DHR_OK) {
+        std::fprintf(stderr, "%s\n", c->err.c_str());
+        delete c;
+        return st;
+    }
     *out = c;
     return DHR_OK;
 }

@@ -16,6 +16,7 @@ struct dhr_ctx {
     int n_cu = 0;
     std::string err;
     uint64_t* trace_counters = nullptr;  // instrumentation (dhr_set_trace_counters)
+    void* scratch = nullptr;             // device address of this device's filter scratch (dhr_svgf_filter_noalloc)
 };
 
 // Device-resident BVH.  Node: 4 x 16 bytes (two child boxes + child refs);
@@ -72,6 +73,10 @@ class DeviceGuard {
 
 // Checks the launch(es) just enqueued.
 dhr_status check_launch(dhr_ctx* ctx, const char* what);
+
+// Sets ctx->scratch to the device address of the no-alloc filter's scratch on
+// ctx->device (looked up once per device).
+dhr_status svgf_scratch_init(dhr_ctx* ctx);
 
 // Host image of the device description of a two-level hierarchy (the
 // layout of the kernels' TwoLevel: instance records, then the node and

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <vector>
 
 #include "svgf_common.h"
@@ -683,30 +684,51 @@ uint64_t dhr_svgf_workspace_bytes(uint32_t W, uint32_t H, const dhr_svgf_params*
     return HW * 16 + 2 * HW * 8 + HW * 16 + tiles * 24;
 }
 
-dhr_status dhr_svgf_filter(dhr_ctx* ctx, const dhr_svgf_params* params, const dhr_svgf_frame* frames,
-                           uint32_t n_frames, dhr_stream stream) {
-    using namespace dhr;
-    if (!ctx) return DHR_ERR_INVALID_ARG;
-    dhr_status st = check_params(ctx, params, "dhr_svgf_filter");
+}  // extern "C"
+
+namespace dhr {
+namespace {
+
+// The filter of dhr_svgf_filter and dhr_svgf_filter_noalloc.  With
+// `scratch` NULL every frame brings its own work buffer; otherwise the
+// frames' work buffers are consecutive 256-byte-aligned slices of
+// `scratch` (of `scratch_bytes` bytes) and their own `work` must be NULL.
+dhr_status filter_impl(dhr_ctx* ctx, const dhr_svgf_params* params, const dhr_svgf_frame* frames, uint32_t n_frames,
+                       dhr_stream stream, char* scratch, uint64_t scratch_bytes, const char* what) {
+    dhr_status st = check_params(ctx, params, what);
     if (st != DHR_OK) return st;
-    if (n_frames && !frames) return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_filter: frames is NULL");
+    if (n_frames && !frames) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: frames is NULL", what);
     std::vector<SvgfDesc> descs(n_frames);
+    uint64_t used = 0;
     for (uint32_t k = 0; k < n_frames; ++k) {
         const dhr_svgf_frame& F = frames[k];
-        if (!sz_ok(F.W, F.H)) return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_filter: frame %u: bad size", k);
-        if (F.n_ao == 0) return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_filter: frame %u: n_ao == 0", k);
-        if (!F.ao_count || !F.pos || !F.nz || !F.dz || !F.mv || !F.hist_out || !F.out || !F.work)
-            return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_filter: frame %u: missing buffer", k);
+        if (!sz_ok(F.W, F.H)) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: frame %u: bad size", what, k);
+        if (F.n_ao == 0) return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: frame %u: n_ao == 0", what, k);
+        if (!F.ao_count || !F.pos || !F.nz || !F.dz || !F.mv || !F.hist_out || !F.out || (!scratch && !F.work))
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: frame %u: missing buffer", what, k);
+        if (scratch && F.work)
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: frame %u: work must be NULL (the library's scratch is used)",
+                             what, k);
         if (F.hist_in && (!F.prev_pos || !F.prev_nz))
-            return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_filter: frame %u: hist_in needs prev_pos/prev_nz", k);
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: frame %u: hist_in needs prev_pos/prev_nz", what, k);
         if (F.hist_in && F.hist_in == F.hist_out)
-            return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_filter: frame %u: hist_out aliases hist_in", k);
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: frame %u: hist_out aliases hist_in", what, k);
         if (!aligned16(F.pos) || !aligned16(F.nz) || !aligned16(F.hist_out) || !aligned8(F.dz) || !aligned8(F.mv) ||
             (F.hist_in && (!aligned16(F.hist_in) || !aligned16(F.prev_pos) || !aligned16(F.prev_nz))) ||
             (F.save && !aligned8(F.save)) || (F.work && !aligned8(F.work)))
-            return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_filter: frame %u: misaligned buffer", k);
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: frame %u: misaligned buffer", what, k);
         if (!(F.pix > 0.0f) || !std::isfinite(F.pix))
-            return set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_svgf_filter: frame %u: pix must be positive", k);
+            return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: frame %u: pix must be positive", what, k);
+        float* work = F.work;
+        if (scratch) {
+            const uint64_t need = (dhr_svgf_workspace_bytes(F.W, F.H, params, 0) + 255) & ~uint64_t(255);
+            if (used + need > scratch_bytes)
+                return set_error(ctx, DHR_ERR_INVALID_ARG,
+                                 "%s: the frames need more than the %llu bytes of scratch (%llu through frame %u)", what,
+                                 (unsigned long long)scratch_bytes, (unsigned long long)(used + need), k);
+            work = reinterpret_cast<float*>(scratch + used);
+            used += need;
+        }
         SvgfDesc& d = descs[k];
         std::memset(&d, 0, sizeof d);
         d.W = F.W;
@@ -724,15 +746,15 @@ dhr_status dhr_svgf_filter(dhr_ctx* ctx, const dhr_svgf_params* params, const dh
         d.hist_out = reinterpret_cast<float4*>(F.hist_out);
         d.out = F.out;
         d.save = reinterpret_cast<float2*>(F.save);
-        d.work = reinterpret_cast<float2*>(F.work);
-        d.ke = reinterpret_cast<float*>(F.work) + (size_t)F.W * F.H * 4;
-        d.fb = reinterpret_cast<uint32_t*>(F.work) + (size_t)F.W * F.H * 5;
+        d.work = reinterpret_cast<float2*>(work);
+        d.ke = work + (size_t)F.W * F.H * 4;
+        d.fb = reinterpret_cast<uint32_t*>(work) + (size_t)F.W * F.H * 5;
         d.pix = F.pix;
     }
     DeviceGuard g(ctx->device);
     const SvgfK K = kparams(params);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    st = for_chunks(ctx, descs, "dhr_svgf_filter", K.levels, s, K, [&](const SvgfBatch& B, dim3 grid) {
+    st = for_chunks(ctx, descs, what, K.levels, s, K, [&](const SvgfBatch& B, dim3 grid) {
         hipLaunchKernelGGL(temporal_kernel, grid, dim3(kSvgfBlock), 0, s, B, K);
         switch (K.R) {
             case 0: hipLaunchKernelGGL(variance_kernel<0>, grid, dim3(kSvgfBlock), 0, s, B, K); break;
@@ -742,6 +764,56 @@ dhr_status dhr_svgf_filter(dhr_ctx* ctx, const dhr_svgf_params* params, const dh
         }
     });
     return st;
+}
+
+// Scratch of dhr_svgf_filter_noalloc: one array per device, held while the
+// library is loaded.  Host code never passes `scratch` itself to a kernel or
+// a copy (on the host it names a stand-in, not device memory); it uses the
+// device address that svgf_scratch_init looked up for each device.
+constexpr uint64_t kNoAllocScratchBytes = DHR_SVGF_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+// Looks up the device address of `scratch` on the context's device, once per
+// device, with that device current (called by dhr_create).
+dhr_status svgf_scratch_init(dhr_ctx* ctx) {
+    if (ctx->device < 0 || ctx->device >= kMaxDevices)
+        return set_error(ctx, DHR_ERR_UNSUPPORTED, "dhr_create: device %d beyond %d", ctx->device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[ctx->device]) {
+        DeviceGuard g(ctx->device);
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(ctx, DHR_ERR_DEVICE, "dhr_create: no address for the filter's scratch: %s",
+                             hipGetErrorString(e));
+        g_scratch_ptr[ctx->device] = p;
+    }
+    ctx->scratch = g_scratch_ptr[ctx->device];
+    return DHR_OK;
+}
+
+}  // namespace dhr
+
+extern "C" {
+
+dhr_status dhr_svgf_filter(dhr_ctx* ctx, const dhr_svgf_params* params, const dhr_svgf_frame* frames,
+                           uint32_t n_frames, dhr_stream stream) {
+    if (!ctx) return DHR_ERR_INVALID_ARG;
+    return dhr::filter_impl(ctx, params, frames, n_frames, stream, nullptr, 0, "dhr_svgf_filter");
+}
+
+dhr_status dhr_svgf_filter_noalloc(dhr_ctx* ctx, const dhr_svgf_params* params, const dhr_svgf_frame* frames,
+                                   uint32_t n_frames, dhr_stream stream) {
+    if (!ctx) return DHR_ERR_INVALID_ARG;
+    if (!ctx->scratch) return dhr::set_error(ctx, DHR_ERR_DEVICE, "dhr_svgf_filter_noalloc: no scratch on this device");
+    return dhr::filter_impl(ctx, params, frames, n_frames, stream, static_cast<char*>(ctx->scratch),
+                            dhr::kNoAllocScratchBytes, "dhr_svgf_filter_noalloc");
 }
 
 dhr_status dhr_svgf_spatial_forward(dhr_ctx* ctx, const dhr_svgf_params* params, const dhr_svgf_spatial_frame* frames,
