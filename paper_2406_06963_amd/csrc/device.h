@@ -152,6 +152,16 @@ __device__ __forceinline__ NodeRec load_node_uniform(const float4* __restrict__ 
 // already keeps busy; both measured slower.)
 // Returns each child's entry and exit distance (entry clamped to 0); the
 // child is hit where entry <= min(exit, tmax).
+//
+// OCT >= 0: every live lane's direction has the sign pattern OCT (bit k set:
+// axis k negative), so the entry plane of each axis is known at compile time
+// (the lower plane for a positive direction, the upper for a negative one)
+// and the min / max pairs drop out: 23 VALU per node instead of 35.  The
+// plane distances are fma(plane, 1/d, -o/d), monotone in the plane, so the
+// picked plane is the one the min / max would pick, bit for bit.  Lanes
+// whose signs differ may only be dead ones (tmax < 0: an entry >= 0 never
+// passes entry <= tmax).
+template <int OCT = -1>
 __device__ __forceinline__ void box_test(const NodeRec& n, float3 id, float3 ood, float& a_in, float& a_out,
                                          float& b_in, float& b_out, int& c0, int& c1) {
     const float4 a = n.a, b = n.b, c = n.c;
@@ -162,12 +172,30 @@ __device__ __forceinline__ void box_test(const NodeRec& n, float3 id, float3 ood
     const float bx0 = fmaf(b.x, id.x, -ood.x), bx1 = fmaf(b.y, id.x, -ood.x);
     const float by0 = fmaf(b.z, id.y, -ood.y), by1 = fmaf(b.w, id.y, -ood.y);
     const float bz0 = fmaf(c.z, id.z, -ood.z), bz1 = fmaf(c.w, id.z, -ood.z);
-    a_in = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
-    a_out = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fmaxf(az0, az1));
-    b_in = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
-    b_out = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fmaxf(bz0, bz1));
+    if constexpr (OCT < 0) {
+        a_in = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
+        a_out = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fmaxf(az0, az1));
+        b_in = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
+        b_out = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fmaxf(bz0, bz1));
+    } else {
+        constexpr bool nx = OCT & 1, ny = OCT & 2, nz = OCT & 4;
+        a_in = fmaxf(fmaxf(nx ? ax1 : ax0, ny ? ay1 : ay0), fmaxf(nz ? az1 : az0, 0.0f));
+        a_out = fminf(fminf(nx ? ax0 : ax1, ny ? ay0 : ay1), nz ? az0 : az1);
+        b_in = fmaxf(fmaxf(nx ? bx1 : bx0, ny ? by1 : by0), fmaxf(nz ? bz1 : bz0, 0.0f));
+        b_out = fminf(fminf(nx ? bx0 : bx1, ny ? by0 : by1), nz ? bz0 : bz1);
+    }
     c0 = ch.x;
     c1 = ch.y;
+}
+
+// The sign pattern shared by the live lanes' directions (bit k: axis k
+// negative, as the sign of the clamped inverse), or -1 if they differ.
+__device__ __forceinline__ int wave_octant(float3 id, bool live) {
+    const uint64_t L = __ballot(live);
+    const uint64_t sx = __ballot(live && id.x < 0.0f), sy = __ballot(live && id.y < 0.0f),
+                   sz = __ballot(live && id.z < 0.0f);
+    if ((sx != 0 && sx != L) || (sy != 0 && sy != L) || (sz != 0 && sz != L)) return -1;
+    return (sx ? 1 : 0) | (sy ? 2 : 0) | (sz ? 4 : 0);
 }
 
 // Moller-Trumbore in fp32 (two-sided, edges inclusive) of the triangle
@@ -194,12 +222,19 @@ __device__ __forceinline__ float tri_t_uniform(const float4* __restrict__ tris, 
     return tri_t_rec(v0, ld_const(tris, 3 * i + 1), ld_const(tris, 3 * i + 2), o, d);
 }
 
-// Whether the ray hits triangle i at 0 < t < tmax: the Moller-Trumbore
-// tests with the barycentrics and t left unnormalised (multiplied by det,
-// signed by det), so no division is needed.
-__device__ __forceinline__ bool tri_hits_uniform(const float4* __restrict__ tris, int i, float3 o, float3 d,
-                                                 float tmax) {
-    const float4 v0 = ld_const(tris, 3 * i), e1 = ld_const(tris, 3 * i + 1), e2 = ld_const(tris, 3 * i + 2);
+// A triangle record (v0 + original index, e1 + object id, e2).
+struct TriRec {
+    float4 v0, e1, e2;
+};
+__device__ __forceinline__ TriRec load_tri_uniform(const float4* __restrict__ tris, int i) {
+    return TriRec{ld_const(tris, 3 * i), ld_const(tris, 3 * i + 1), ld_const(tris, 3 * i + 2)};
+}
+
+// Whether the ray hits triangle (v0, e1, e2) at 0 < t < tmax: the
+// Moller-Trumbore tests with the barycentrics and t left unnormalised
+// (multiplied by det, signed by det), so no division is needed.
+__device__ __forceinline__ bool tri_hits_rec(const TriRec& r, float3 o, float3 d, float tmax) {
+    const float4 v0 = r.v0, e1 = r.e1, e2 = r.e2;
     const float3 E1 = f3(e1), E2 = f3(e2);
     const float3 p = cross3(d, E2);
     const float det = dot3(E1, p);
@@ -211,6 +246,41 @@ __device__ __forceinline__ bool tri_hits_uniform(const float4* __restrict__ tris
     const float T = __uint_as_float(fbits(dot3(E2, q)) ^ sgn);
     const float ad = fabsf(det);
     return (U >= 0.0f) & (V >= 0.0f) & (U + V <= ad) & (T > 0.0f) & (T < tmax * ad);
+}
+
+__device__ __forceinline__ bool tri_hits_uniform(const float4* __restrict__ tris, int i, float3 o, float3 d,
+                                                 float tmax) {
+    return tri_hits_rec(load_tri_uniform(tris, i), o, d, tmax);
+}
+
+// Two consecutive records i, i + 1 (96 bytes) as one 64- and one 32-byte
+// scalar load, so both are in flight before either is tested.
+typedef float vf16 __attribute__((ext_vector_type(16)));
+typedef float vf8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ void load_tri_pair_uniform(const float4* __restrict__ tris, int i, TriRec& a, TriRec& b) {
+    const vf16 p = *(const __attribute__((address_space(4))) vf16*)(tris + 3 * i);
+    const vf8 q = *(const __attribute__((address_space(4))) vf8*)(tris + 3 * i + 4);
+    a = TriRec{make_float4(p[0], p[1], p[2], p[3]), make_float4(p[4], p[5], p[6], p[7]),
+               make_float4(p[8], p[9], p[10], p[11])};
+    b = TriRec{make_float4(p[12], p[13], p[14], p[15]), make_float4(q[0], q[1], q[2], q[3]),
+               make_float4(q[4], q[5], q[6], q[7])};
+}
+
+// The triangles [first, first + count) of a leaf two at a time: a pair's
+// records arrive by one request, so a leaf pays one load latency per pair
+// instead of one per triangle; an odd last triangle is loaded alone (the
+// record after it may lie beyond the array).  test(rec, index) is called in
+// index order.
+template <class Test>
+__device__ __forceinline__ void leaf_pairs(const float4* __restrict__ tris, int first, int count, Test test) {
+    int k = 0;
+    for (; k + 1 < count; k += 2) {
+        TriRec a, b;
+        load_tri_pair_uniform(tris, first + k, a, b);
+        test(a, first + k);
+        test(b, first + k + 1);
+    }
+    if (k < count) test(load_tri_uniform(tris, first + k), first + k);
 }
 
 __device__ __forceinline__ void leaf_range(int ref, int& first, int& count) {
@@ -245,7 +315,7 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // With COUNT, `cnt` tallies the work of this lane's own ray: the nodes and
 // leaves whose boxes it hits (a bit stack beside the wave's stack records
 // whether it hit each pushed child) and the triangles of those leaves.
-template <bool COUNT, class Leaf, class Done>
+template <bool COUNT, int OCT, class Leaf, class Done>
 __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, float3 id, float3 ood,
                                             const float& tmax, bool live, int* wstk, Leaf visit_leaf, Done done,
                                             TravCount* cnt) {
@@ -257,7 +327,7 @@ __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, fl
             float t0, x0, t1, x1;
             int c0, c1;
             if (COUNT && in) ++cnt->nodes;
-            box_test(load_node_uniform(nodes, node), id, ood, t0, x0, t1, x1, c0, c1);
+            box_test<OCT>(load_node_uniform(nodes, node), id, ood, t0, x0, t1, x1, c0, c1);
             c0 = uniform(c0);
             c1 = uniform(c1);
             // hit masks: entry <= exit and entry <= tmax, each compare's own lane
@@ -299,6 +369,25 @@ __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, fl
     }
 }
 
+// packet_walk with the box test specialised for the wave's direction signs
+// when the live lanes share them (shadow rays towards one light, most
+// primary-ray waves), the generic one otherwise (ambient-occlusion rays).
+template <bool COUNT, class Leaf, class Done>
+__device__ __forceinline__ void walk(const float4* __restrict__ nodes, float3 id, float3 ood, const float& tmax,
+                                     bool live, int* wstk, Leaf leaf, Done done, TravCount* cnt) {
+    switch (wave_octant(id, live)) {
+        case 0: packet_walk<COUNT, 0>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        case 1: packet_walk<COUNT, 1>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        case 2: packet_walk<COUNT, 2>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        case 3: packet_walk<COUNT, 3>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        case 4: packet_walk<COUNT, 4>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        case 5: packet_walk<COUNT, 5>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        case 6: packet_walk<COUNT, 6>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        case 7: packet_walk<COUNT, 7>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        default: packet_walk<COUNT, -1>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+    }
+}
+
 // Any hit at 0 < t < r.tmax for the lanes with `live`; the others return false.
 template <bool COUNT = false>
 __device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const float4* __restrict__ tris, const Ray& r,
@@ -308,6 +397,8 @@ __device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const 
     const float3 ood = f3(r.o.x * id.x, r.o.y * id.y, r.o.z * id.z);
     float tmax = live ? r.tmax : -1.0f;
     bool hit = false;
+    // (one triangle at a time: loading pairs here, as closest_hit does,
+    // measured slower on the visibility rays)
     auto leaf = [&](int first, int count) {
         for (int k = 0; k < count; ++k) {
             if (tri_hits_uniform(tris, first + k, r.o, r.d, tmax)) {  // false for finished lanes (tmax < 0)
@@ -317,7 +408,7 @@ __device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const 
         }
     };
     auto done = [&] { return !__any(tmax >= 0.0f); };
-    packet_walk<COUNT>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt);
+    walk<COUNT>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt);
     return hit;
 }
 
@@ -333,18 +424,18 @@ __device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, con
     uint32_t best_orig = 0xFFFFFFFFu;
     tbest = live ? __builtin_inff() : -1.0f;
     auto leaf = [&](int first, int count) {
-        for (int k = 0; k < count; ++k) {
-            uint32_t orig;
-            const float t = tri_t_uniform(tris, first + k, o, d, &orig);
+        leaf_pairs(tris, first, count, [&](const TriRec& rec, int k) {
+            const uint32_t orig = fbits(rec.v0.w);
+            const float t = tri_t_rec(rec.v0, rec.e1, rec.e2, o, d);
             if (t > 0.0f && t <= tbest && (t < tbest || orig < best_orig)) {
                 tbest = t;
-                best = first + k;
+                best = k;
                 best_orig = orig;
             }
-        }
+        });
     };
     auto done = [] { return false; };
-    packet_walk<COUNT>(nodes, id, ood, tbest, live, wstk, leaf, done, cnt);
+    walk<COUNT>(nodes, id, ood, tbest, live, wstk, leaf, done, cnt);
     if (!live) tbest = __builtin_inff();
     return best;
 }
@@ -387,7 +478,7 @@ __device__ __forceinline__ void walk_bottom(const float4* __restrict__ nodes, fl
     const float3 id = safe_inv(d);
     const float3 ood = f3(o.x * id.x, o.y * id.y, o.z * id.z);
     const bool live = tmax >= 0.0f;
-    packet_walk<false>(nodes, id, ood, tmax, live, wstk, leaf, done, nullptr);
+    packet_walk<false, -1>(nodes, id, ood, tmax, live, wstk, leaf, done, nullptr);
 }
 
 // any_hit through a two-level hierarchy (`top` its top-level nodes); wstk2
@@ -417,7 +508,7 @@ __device__ __forceinline__ bool any_hit_2l(const float4* __restrict__ top, const
             walk_bottom(bottom_nodes(L, b), o, d, tmax, wstk2, leaf, done);
         }
     };
-    packet_walk<false>(top, id, ood, tmax, live, wstk, top_leaf, done, nullptr);
+    packet_walk<false, -1>(top, id, ood, tmax, live, wstk, top_leaf, done, nullptr);
     return hit;
 }
 
@@ -456,7 +547,7 @@ __device__ __forceinline__ void closest_hit_2l(const float4* __restrict__ top, c
             walk_bottom(bottom_nodes(L, b), oo, dd, tbest, wstk2, leaf, done);
         }
     };
-    packet_walk<false>(top, id, ood, tbest, live, wstk, top_leaf, done, nullptr);
+    packet_walk<false, -1>(top, id, ood, tbest, live, wstk, top_leaf, done, nullptr);
     if (!live) tbest = __builtin_inff();
 }
 

@@ -1,17 +1,20 @@
 """One view's frames through the hot path, consecutive frames overlapped.
 
-Frame f's G-buffer and visibility rays are one dhr_gbuffer_trace launch on
-one stream; its filter (dhr_svgf_filter: temporal accumulation, variance,
-a-trous levels, Section 3.3) runs on a second stream.  Frame f + 1's
-G-buffer + visibility launch therefore runs beside frame f's filter, which
-fills the device where one pass alone leaves it idle (the tail of the
-traversal kernel, the filter's launch boundaries).  Three G-buffer / count
-slots and two history buffers make the overlap safe: frame f + 1 writes slot
-(f + 1) % 3 only after frame f - 1's filter, the last reader of that slot,
-has finished.  The results are those of the frames run one at a time
+Frame f's G-buffer and visibility rays are one dhr_gbuffer_trace launch;
+its filter (dhr_svgf_filter: temporal accumulation, variance, a-trous levels,
+Section 3.3) runs on a filter stream.  With `frames_in_flight` = D, the
+G-buffer + visibility launches of frames f + 1 .. f + D run on D streams
+beside frame f's filter and beside each other: a frame's rays do not depend
+on any other frame, so the long primary walks at the end of one frame's
+launch (grazing rays at the horizon) leave the device to the next frame's
+rays instead of idling it, and the filter's launch boundaries are filled
+the same way.  D + 2 G-buffer / count slots and two history buffers make the
+overlap safe: frame f writes slot f % (D + 2) only after the filter of frame
+f - D - 1, the last reader of that slot (as its previous frame), has
+finished.  The results are those of the frames run one at a time
 (`overlap=False`), byte for byte.
 
-Both streams have the default priority.  One pipeline object serves one view;
+All streams have the default priority.  One pipeline object serves one view;
 its buffers are reused by every run, so runs of one object must not overlap.
 """
 from __future__ import annotations
@@ -26,32 +29,38 @@ class FramePipeline:
     (the filter's denominator); n_lights: lights of the trace parameters;
     params: the filter's dhr_svgf_params."""
 
-    def __init__(self, ctx, bvh, W: int, H: int, n_ao: int, n_lights: int, params, device: str = "cuda"):
+    def __init__(self, ctx, bvh, W: int, H: int, n_ao: int, n_lights: int, params, device: str = "cuda",
+                 frames_in_flight: int = 1):
         import torch
         self.torch = torch
         self.ctx, self.bvh, self.W, self.H, self.n_ao, self.P = ctx, bvh, W, H, n_ao, params
         HW = W * H
-        self.gb = [B.gbuffer_tensors(W, H, device) for _ in range(3)]
-        self.aos = [torch.empty(HW, dtype=torch.uint8, device=device) for _ in range(3)]
-        self.shs = [torch.empty(max(n_lights, 1), HW, dtype=torch.uint8, device=device) for _ in range(3)]
+        self.depth = max(1, int(frames_in_flight))
+        self.slots = S = self.depth + 2
+        self.gb = [B.gbuffer_tensors(W, H, device) for _ in range(S)]
+        self.aos = [torch.empty(HW, dtype=torch.uint8, device=device) for _ in range(S)]
+        self.shs = [torch.empty(max(n_lights, 1), HW, dtype=torch.uint8, device=device) for _ in range(S)]
         self.n_lights = n_lights
         self.hist = [torch.empty(HW, 4, device=device) for _ in range(2)]
         self.out = torch.empty(HW, device=device)
         self.work = torch.empty(B.dhr_svgf_workspace_bytes(W, H, params, 0) // 4, device=device)
-        self.s_frame, self.s_filt = torch.cuda.Stream(), torch.cuda.Stream()
+        self.s_frames = [torch.cuda.Stream() for _ in range(self.depth)]
+        self.s_filt = torch.cuda.Stream()
 
     def launch_frame(self, f: int, cams, tps, stream) -> None:
         """G-buffer and visibility of frame f (cams[f - 1] is its previous camera; frame 0 has none)."""
-        g = self.gb[f % 3]
+        k = f % self.slots
+        g = self.gb[k]
         B.dhr_gbuffer_trace(self.ctx, self.bvh, cams[f], cams[f - 1] if f > 0 else None, self.W, self.H, tps[f],
-                            g["pos"], g["nz"], g["dz"], g["mv"], self.aos[f % 3],
-                            self.shs[f % 3] if self.n_lights else None, stream=stream)
+                            g["pos"], g["nz"], g["dz"], g["mv"], self.aos[k],
+                            self.shs[k] if self.n_lights else None, stream=stream)
 
     def launch_filter(self, f: int, cams, stream) -> None:
         """The filter of frame f on its G-buffer and counts, with frame f - 1's as history."""
-        g, p = self.gb[f % 3], self.gb[(f - 1) % 3]
+        S = self.slots
+        g, p = self.gb[f % S], self.gb[(f - 1) % S]
         first = f == 0
-        fr = B.svgf_frame(self.W, self.H, self.n_ao, self.aos[f % 3], g["pos"], g["nz"], g["dz"], g["mv"],
+        fr = B.svgf_frame(self.W, self.H, self.n_ao, self.aos[f % S], g["pos"], g["nz"], g["dz"], g["mv"],
                           None if first else p["pos"], None if first else p["nz"],
                           None if first else self.hist[(f + 1) % 2], self.hist[f % 2], self.out,
                           B.pix_angle(cams[f], self.H), work=self.work)
@@ -79,31 +88,36 @@ class FramePipeline:
                 self.launch_filter(f, cams, cur)
                 rec("svgf", f, 1, cur)
             return
-        sf, sv = self.s_frame, self.s_filt
-        sf.wait_stream(cur)
+        D, S = self.depth, self.slots
+        sfs, sv = self.s_frames, self.s_filt
+        for s in sfs:
+            s.wait_stream(cur)
         sv.wait_stream(cur)
-        done = {}
+        done, ready = {}, {}
 
         def frame(f):
-            rec("frame", f, 0, sf)
-            self.launch_frame(f, cams, tps, sf)
-            rec("frame", f, 1, sf)
+            s = sfs[f % D]
+            if f - S + 1 >= n0:
+                s.wait_event(done[f - S + 1])    # slot f % S: filter f - S + 1 read it as its previous frame
+            rec("frame", f, 0, s)
+            self.launch_frame(f, cams, tps, s)
+            rec("frame", f, 1, s)
+            e = torch.cuda.Event()
+            e.record(s)
+            ready[f] = e
 
-        if n1 > n0:
-            frame(n0)
+        for f in range(n0, min(n0 + D, n1)):
+            frame(f)
         for f in range(n0, n1):
-            ready = torch.cuda.Event()
-            ready.record(sf)
-            sv.wait_event(ready)                 # filter f after frame f
+            sv.wait_event(ready[f])              # filter f after frame f
             rec("svgf", f, 0, sv)
             self.launch_filter(f, cams, sv)
             rec("svgf", f, 1, sv)
-            if f + 1 < n1:
-                if f > n0:
-                    sf.wait_event(done[f - 1])   # slot (f + 1) % 3 is filter f - 1's previous frame
-                frame(f + 1)
             d = torch.cuda.Event()
             d.record(sv)
             done[f] = d
-        cur.wait_stream(sf)
+            if f + D < n1:
+                frame(f + D)
+        for s in sfs:
+            cur.wait_stream(s)
         cur.wait_stream(sv)

@@ -1,10 +1,11 @@
 """Consecutive frames overlapped on two streams (needs an MI355X).
 
-FramePipeline runs frame f + 1's G-buffer + visibility launch beside frame
-f's filter (the schedule bench.py times).  Over eight frames, in two runs
-(the second continuing the first's history), the filtered output, both
-history buffers, the three G-buffer slots and the counts equal those of the
-same frames run one at a time, bit for bit.
+FramePipeline runs the G-buffer + visibility launches of the next one to
+three frames beside frame f's filter and beside each other (the schedule
+bench.py times).  Over eight frames, in two runs (the second continuing the
+first's history), the filtered output, both history buffers, every G-buffer
+slot and the counts equal those of the same frames run one at a time, bit for
+bit.
 """
 import pytest
 
@@ -33,8 +34,9 @@ def _bits(t):
     return t.view(torch.int32) if t.dtype == torch.float32 else t
 
 
-@pytest.mark.parametrize("preset", ["tiny", "ragged", "room720", "terrain1080"])
-def test_overlapped_frames_equal_one_at_a_time(B, ctx, preset):
+@pytest.mark.parametrize("preset,depth", [("tiny", 1), ("ragged", 2), ("room720", 1), ("room720", 3),
+                                          ("terrain1080", 1), ("terrain1080", 2)])
+def test_overlapped_frames_equal_one_at_a_time(B, ctx, preset, depth):
     import torch
     from paper_2406_06963_amd.pipeline import FramePipeline
     pr = wl.preset(preset)
@@ -48,7 +50,7 @@ def test_overlapped_frames_equal_one_at_a_time(B, ctx, preset):
     P = B.svgf_params(levels=pr.levels, alpha=pr.alpha)
     res = []
     for overlap in (False, True):
-        pipe = FramePipeline(ctx, bvh, pr.W, pr.H, pr.n_ao, len(lights), P)
+        pipe = FramePipeline(ctx, bvh, pr.W, pr.H, pr.n_ao, len(lights), P, frames_in_flight=depth)
         pipe.run(cams, tps, 0, 5, overlap=overlap)
         pipe.run(cams, tps, 5, n, overlap=overlap)
         torch.cuda.synchronize()
@@ -56,4 +58,5 @@ def test_overlapped_frames_equal_one_at_a_time(B, ctx, preset):
                    + pipe.aos + pipe.shs)
     for k, (a, b) in enumerate(zip(*res)):
         assert torch.equal(_bits(a), _bits(b)), k
-    print(f"{preset}: {n} overlapped frames equal the frames run one at a time", flush=True)
+    print(f"{preset}, {depth} frame(s) in flight: {n} overlapped frames equal the frames run one at a time",
+          flush=True)
