@@ -22,13 +22,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# fp32 vector peak without packed-FP32 instructions (the build disables them):
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
-VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# fp32 operations per traversal step, counted from the kernel source
-FLOPS_PER_NODE = 50      # two slab tests: 12 FMA (24) + 24 min/max + 2 compares
-FLOPS_PER_TRI = 48       # Moller-Trumbore without division: 2 cross (18), 4 dot (20), o - v0 (3),
-                         # u + v and tmax |det| (2), 5 compares
+# VALU issue peak in lane operations (slots) per second without packed-FP32
+# instructions (the build disables them): 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz; an FMA is one slot, a transcendental (exp2, log2, rcp, sqrt) four
+# (quarter rate)
+VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
+SLOT_UNIT = "T VALU lane-ops/s"
+# algorithmic VALU slots per unit of work
+SLOTS_PER_NODE = 40      # one node visit: two child slab tests (12 FMA, 12 min/max, entry/exit reductions) and
+                         # the hit and order compares
+SLOTS_PER_TRI = 35       # one ray-triangle test: Moller-Trumbore without division (2 cross, 4 dot, o - v0,
+                         # u + v, t bound, 5 compares)
+# one a-trous level per pixel: 24 non-centre taps x (13 plain slots: normal
+# dot, clamp, the two differences, three exponent FMAs, four accumulations;
+# plus exp2 and log2 at 4 each) = 24 x 21, one depth reciprocal per mirrored
+# tap pair with its span (12 x 6), and the prefilter, its square root and
+# reciprocal and the normalisation (34)
+SLOTS_PER_LEVEL_PX = 24 * 21 + 12 * 6 + 34
+# the adjoint of one level per pixel: pass A forms each tap weight (24 x 24)
+# and its adjoint terms (24 x 18) plus the per-pixel terms (40); pass B forms
+# each neighbour's weight again (24 x 24: storing 24 weights per pixel would
+# cost more HBM time than forming them) and gathers (24 x 12, + 20)
+SLOTS_PER_ADJ_LEVEL_PX = 24 * 24 + 24 * 18 + 40 + 24 * 24 + 24 * 12 + 20
 
 # Hardware byte counters of the dominant kernels, per launch, from the
 # committed rocprofv3 --pmc summary; each entry holds the SHA-256 of the
@@ -124,7 +139,7 @@ def main():
     pr = wl.preset(args.preset)
     W, H = pr.W, pr.H
     HW = W * H
-    nfr = args.warmup + max(args.steps, args.cpu_frames) + 1
+    nfr = args.warmup + max(args.steps, args.cpu_frames) + 6   # + the batched-filter frames
     scene = wl.make_scene(pr.scene)
     cams = wl.camera_path(pr.camera, nfr, scene)
     lights = wl.lights_for(pr.scene)
@@ -219,27 +234,29 @@ def main():
                  "algorithmic_bytes_per_px": svgf_bytes_per_px(pr.levels)}
     roof_trace = None
     if counts:
-        flops = counts[1] * FLOPS_PER_NODE + counts[3] * FLOPS_PER_TRI
-        ach = flops / trace_s / 1e12
-        roof_trace = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                      "frac": ach / VALU_PEAK_TFLOPS, "traffic": pmc_traffic("trace_kernel"),
-                      "kernel": "trace_visibility",
+        slots = counts[1] * SLOTS_PER_NODE + counts[3] * SLOTS_PER_TRI
+        ach = slots / trace_s / 1e12
+        roof_trace = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TSLOTS, "unit": SLOT_UNIT,
+                      "frac": ach / VALU_PEAK_TSLOTS, "traffic": pmc_traffic("trace_kernel"),
+                      "kernel": "trace_kernel (dhr_trace_visibility)", "launch_ms": per["trace"],
                       "traced_rays": counts[0], "node_visits": counts[1], "leaf_visits": counts[2],
-                      "tri_tests": counts[3], "flops_per_node": FLOPS_PER_NODE, "flops_per_tri": FLOPS_PER_TRI}
+                      "tri_tests": counts[3], "slots_per_node": SLOTS_PER_NODE, "slots_per_tri": SLOTS_PER_TRI,
+                      "slots_per_launch": slots}
     roof_frame = roof_frame_seq = None
     if counts_frame:
-        flops = counts_frame[1] * FLOPS_PER_NODE + counts_frame[3] * FLOPS_PER_TRI
-        ach = flops / frame_s / 1e12
-        roof_frame = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                      "frac": ach / VALU_PEAK_TFLOPS, "traffic": pmc_traffic("frame_kernel"),
-                      "kernel": "gbuffer_trace (frame_kernel: primary + visibility rays; its timed launches "
-                                "overlap the previous frame's filter)",
+        slots = counts_frame[1] * SLOTS_PER_NODE + counts_frame[3] * SLOTS_PER_TRI
+        ach = slots / frame_s / 1e12
+        roof_frame = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TSLOTS, "unit": SLOT_UNIT,
+                      "frac": ach / VALU_PEAK_TSLOTS, "traffic": pmc_traffic("frame_kernel"),
+                      "kernel": "frame_kernel (dhr_gbuffer_trace: primary + visibility rays; its timed launches "
+                                "overlap the previous frame's filter)", "launch_ms": per["frame"],
                       "traced_rays": counts_frame[0], "node_visits": counts_frame[1],
                       "leaf_visits": counts_frame[2], "tri_tests": counts_frame[3],
-                      "flops_per_node": FLOPS_PER_NODE, "flops_per_tri": FLOPS_PER_TRI}
-        ach_seq = flops / (per["frame_seq"] / 1e3) / 1e12
-        roof_frame_seq = {"bound": "alu", "achieved": ach_seq, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                          "frac": ach_seq / VALU_PEAK_TFLOPS, "kernel": "frame_kernel, launched alone"}
+                      "slots_per_node": SLOTS_PER_NODE, "slots_per_tri": SLOTS_PER_TRI, "slots_per_launch": slots}
+        ach_seq = slots / (per["frame_seq"] / 1e3) / 1e12
+        roof_frame_seq = {"bound": "alu", "achieved": ach_seq, "peak": VALU_PEAK_TSLOTS, "unit": SLOT_UNIT,
+                          "frac": ach_seq / VALU_PEAK_TSLOTS, "kernel": "frame_kernel, launched alone",
+                          "launch_ms": per["frame_seq"]}
     # the dominant kernel: the larger of the two passes run one at a time
     dominant = "frame" if per["frame_seq"] >= per["svgf_seq"] else "svgf"
     roofline = (roof_frame if (dominant == "frame" and roof_frame) else roof_svgf)
@@ -255,6 +272,7 @@ def main():
         "config": {"workload": f"{pr.name}: {W}x{H}, {pr.scene} scene ({scene.n_tris} tris), "
                                f"{pr.n_ao} AO ray (r={pr.ao_radius}) + {pr.n_shadow} soft-shadow rays/px, "
                                f"{pr.levels}-level SVGF", "frames": args.steps,
+                   "timed_frames": f"{w0}-{w1 - 1} of the camera path (frames 0-{w0 - 1} untimed warmup)",
                    "parallelism": "single GPU"},
         "trace_mrays_s": rays_per_step / trace_s / 1e6,
         "svgf_mpix_s": HW / svgf_s / 1e6,
@@ -308,6 +326,9 @@ def main():
         two_ms = sum(a.elapsed_time(b) for a, b in e2) / n2
         line["svgf_ao_and_shadow"] = {"ms": two_ms, "mpix_s": 2 * HW / (two_ms / 1e3) / 1e6,
                                       "vs_ao_only": two_ms / per["svgf_seq"]}
+
+    line["svgf_levels"] = bench_svgf_levels(B, ctx, W, H, P, gb[f_end % 2], out_s)
+    line["svgf_batch4"] = bench_svgf_batch(B, ctx, bvh, pr, cams, lights, P, f_end, 4)
 
     # the lighter filter (one level of the 3x3 kernel) beside the full one, each
     # with its own history over the same noisy frames; both scored against a
@@ -409,6 +430,85 @@ def main():
     if args.cpu_frames > 0:
         line["cpu_baseline"] = cpu_baseline(pr, scene, cams, lights, args)
     print(json.dumps(line), flush=True)
+
+
+def _median_ms(fn, reps=10):
+    import numpy as np
+    import torch
+    fn()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def bench_svgf_levels(B, ctx, W, H, P, g, scratch):
+    """Each a-trous level's time on one 1080p frame: the spatial stack run
+    with 1 .. L levels on the (c, var) the filter's variance pass produced,
+    level l's time the difference of the medians of l + 1 and l levels; its
+    VALU roofline in algorithmic slots (SLOTS_PER_LEVEL_PX per pixel)."""
+    import torch
+    HW = W * H
+    L = P.levels
+    cv = torch.rand(HW, 2, device="cuda")
+    cv[:, 1] *= 0.05
+    work = torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device="cuda")
+    t = [0.0]
+    for n in range(1, L + 1):
+        Pn = B.svgf_params(levels=n, alpha=P.alpha)
+        fr = [B.spatial_frame(W, H, cv, g["nz"], g["dz"], scratch, work=work)]
+        t.append(_median_ms(lambda: B.dhr_svgf_spatial_forward(ctx, Pn, fr)))
+    lv = []
+    for l in range(L):
+        ms = t[l + 1] - t[l]
+        ach = SLOTS_PER_LEVEL_PX * HW / (ms / 1e3) / 1e12 if ms > 0 else None
+        lv.append({"level": l, "ms": ms, "bound": "alu", "unit": SLOT_UNIT, "peak": VALU_PEAK_TSLOTS,
+                   "achieved": ach, "frac": ach / VALU_PEAK_TSLOTS if ach else None,
+                   "hbm_frac": 40 * HW / (ms / 1e3) / 1e9 / HBM_PEAK_GBS if ms > 0 else None})
+    return {"note": "level l = median of the stack with l + 1 levels minus that with l (one 1080p frame, its "
+                    "geometry, synthetic (c, var)); slots per pixel and level: " + str(SLOTS_PER_LEVEL_PX),
+            "stack_ms": t[1:], "levels": lv}
+
+
+def bench_svgf_batch(B, ctx, bvh, pr, cams, lights, P, f0, n):
+    """The filter over a batch of n consecutive 1080p frames in one call (one
+    launch per pass for all of them): the working set (about 0.3 GB per
+    frame) exceeds the 256 MB last-level cache, so the passes stream from
+    HBM."""
+    import torch
+    W, H, HW = pr.W, pr.H, pr.W * pr.H
+    gb = [B.gbuffer_tensors(W, H) for _ in range(n + 1)]
+    aos = [torch.empty(HW, dtype=torch.uint8, device="cuda") for _ in range(n + 1)]
+    sh = torch.empty(max(len(lights), 1), HW, dtype=torch.uint8, device="cuda")
+    hin = [torch.rand(HW, 4, device="cuda") for _ in range(n)]
+    for h in hin:
+        h[:, 3] = 8.0
+    hout = [torch.empty(HW, 4, device="cuda") for _ in range(n)]
+    outs = [torch.empty(HW, device="cuda") for _ in range(n)]
+    works = [torch.empty(B.dhr_svgf_workspace_bytes(W, H, P, 0) // 4, device="cuda") for _ in range(n)]
+    for k in range(n + 1):
+        f = f0 + k
+        g = gb[k]
+        B.dhr_gbuffer_trace(ctx, bvh, cams[f], cams[f - 1], W, H,
+                            B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao, ao_radius=pr.ao_radius,
+                                           n_shadow=pr.n_shadow, lights=lights),
+                            g["pos"], g["nz"], g["dz"], g["mv"], aos[k], sh)
+    frs = [B.svgf_frame(W, H, pr.n_ao, aos[k + 1], gb[k + 1]["pos"], gb[k + 1]["nz"], gb[k + 1]["dz"],
+                        gb[k + 1]["mv"], gb[k]["pos"], gb[k]["nz"], hin[k], hout[k], outs[k],
+                        B.pix_angle(cams[f0 + k + 1], H), work=works[k]) for k in range(n)]
+    ms = _median_ms(lambda: B.dhr_svgf_filter(ctx, P, frs))
+    nb = svgf_bytes_per_px(P.levels) * HW * n
+    slots = (SLOTS_PER_LEVEL_PX * P.levels) * HW * n
+    return {"frames": n, "ms": ms, "mpix_s": n * HW / (ms / 1e3) / 1e6,
+            "roofline_hbm": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                             "achieved": nb / (ms / 1e3) / 1e9, "frac": nb / (ms / 1e3) / 1e9 / HBM_PEAK_GBS},
+            "roofline_valu_levels": {"bound": "alu", "unit": SLOT_UNIT, "peak": VALU_PEAK_TSLOTS,
+                                     "achieved": slots / (ms / 1e3) / 1e12,
+                                     "frac": slots / (ms / 1e3) / 1e12 / VALU_PEAK_TSLOTS,
+                                     "note": "the a-trous levels' slots over the whole filter's time"}}
 
 
 def bench_light_filter(B, ctx, bvh, pr, cams, lights, gb, ao, sh, P, frames):
@@ -522,15 +622,15 @@ def bench_preset(B, ctx, name, steps, warmup=5):
                             g["pos"], g["nz"], g["dz"], g["mv"], ao, sh)
     B.dhr_set_trace_counters(ctx, None)
     cnt = [int(v) / steps for v in c.cpu().tolist()]
-    flops = cnt[1] * FLOPS_PER_NODE + cnt[3] * FLOPS_PER_TRI
-    ach = flops / (t_f / 1e3) / 1e12
+    slots = cnt[1] * SLOTS_PER_NODE + cnt[3] * SLOTS_PER_TRI
+    ach = slots / (t_f / 1e3) / 1e12
     return {"workload": f"{name}: {W}x{H}, {pr.scene} scene ({scene.n_tris} tris), {pr.n_ao} AO + {pr.n_shadow} "
                         f"shadow rays/px, {pr.levels}-level SVGF", "steps": steps,
             "pass_ms": {"frame": t_f, "svgf": t_s, "gbuf": t_g, "trace": t_t},
             "trace_mrays_s": rays / (t_t / 1e3) / 1e6, "svgf_mpix_s": HW / (t_s / 1e3) / 1e6,
             "step_mrays_s": rays / ((t_f + t_s) / 1e3) / 1e6,
-            "roofline_frame": {"bound": "alu", "unit": "TFLOP/s", "peak": VALU_PEAK_TFLOPS, "achieved": ach,
-                               "frac": ach / VALU_PEAK_TFLOPS, "traced_rays": cnt[0], "node_visits": cnt[1],
+            "roofline_frame": {"bound": "alu", "unit": SLOT_UNIT, "peak": VALU_PEAK_TSLOTS, "achieved": ach,
+                               "frac": ach / VALU_PEAK_TSLOTS, "traced_rays": cnt[0], "node_visits": cnt[1],
                                "tri_tests": cnt[3]},
             "roofline_svgf": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
                               "achieved": svgf_bytes_per_px(pr.levels) * HW / (t_s / 1e3) / 1e9,
@@ -612,12 +712,16 @@ def bench_backward(B, ctx, n_frames):
     fb = px * L * 40
     bb = px * L * 48
     rf = lambda nb, ms: {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "achieved": nb / (ms / 1e3) / 1e9,
-                         "frac": nb / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-                         "note": "VALU-bound: every tap's weight and its derivatives are recomputed"}
+                         "frac": nb / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    rv = lambda per_px, ms: {"bound": "alu", "unit": SLOT_UNIT, "peak": VALU_PEAK_TSLOTS,
+                             "slots_per_px_level": per_px, "achieved": per_px * px * L / (ms / 1e3) / 1e12,
+                             "frac": per_px * px * L / (ms / 1e3) / 1e12 / VALU_PEAK_TSLOTS}
     return {"workload": f"{n_frames} x {W}x{H} room frames, 5 levels, MSE vs 256-spp AO",
             "forward_ms": fw, "backward_ms": bw, "fwd_bwd_ms": fw + bw,
             "fwd_bwd_mpix_s": px / ((fw + bw) / 1e3) / 1e6, "mse": loss0,
             "roofline_forward": rf(fb, fw), "roofline_backward": rf(bb, bw),
+            "roofline_forward_valu": rv(SLOTS_PER_LEVEL_PX, fw),
+            "roofline_backward_valu": rv(SLOTS_PER_ADJ_LEVEL_PX, bw),
             "grad_sigma": gs.cpu().tolist()}
 
 
