@@ -334,59 +334,67 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_a_rows(const BwdBatch Bt, 
             const float2 dzp = D.dz[i];
             const float3 np = f3(n4);
             const float eps_zp = P.eps_z * n4.w;
-            // sweep 1: normaliser and the level's outputs (one tap row per
-            // iteration: unrolling all 25 taps would hoist their LDS reads
-            // and hold them all in registers)
-            float Dn = 0.0f, Sc = 0.0f, Sv = 0.0f;
+            // One sweep over the taps.  The weight adjoint of tap t is
+            //   ww_t = wbar_t w_t = A al_t - (A d + K) be_t + 2 B ga_t
+            // with be_t = h w, al_t = be_t (c_q - c_p), ga_t = be_t^2 v_q and
+            // d = c' - c_p, so each sum over taps of ww_t phi_t (phi: the
+            // sign and size of c_p - c_q, the depth term's sigma factor, the
+            // normal term's log) is a combination of three sums that need
+            // neither A, K nor c' yet: every weight is formed once.  A tap
+            // and its mirror (-a, -b) share the depth reciprocal.  One pair
+            // row per iteration (unrolling all taps would hoist their LDS
+            // reads and hold them all in registers).
+            const float h0 = b3(0) * b3(0);
+            float Dn = h0, Sc = 0.0f, Sv = h0 * h0 * cvp.y;
+            float pa[4] = {0.0f, 0.0f, 0.0f, 0.0f}, pb[4] = {0.0f, 0.0f, 0.0f, 0.0f},
+                  pg[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll 1
-            for (int b = -2; b <= 2; ++b)
+            for (int b = 0; b <= 2; ++b)
 #pragma unroll
             for (int a = -2; a <= 2; ++a) {
-                const int e = c + b * CW + s * a;
-                const float4 nq = s_nz[e];
-                const float2 c2 = s_cv[e];
-                const float w = (a == 0 && b == 0)
-                                    ? 1.0f
-                                    : fused_weight(depth_coef(dzp, a, b, s, sz, eps_zp), ke, n4.w, cvp.x, np, sn, nq, c2.x);
-                const float hw = b3(a) * b3(b) * w;
-                Dn += hw;
-                Sc = fmaf(hw, c2.x - cvp.x, Sc);
-                Sv = fmaf(hw * hw, c2.y, Sv);
-            }
-            const float iD = 1.0f / Dn;
-            const float cpr = fmaf(Sc, iD, cvp.x), vpr = Sv * iD * iD;
-            const float A = ab * iD, Bc = bb * iD * iD;
-            const float K2 = 2.0f * Bc * vpr * Dn;
-            float cbar_c = 0.0f, gbar = 0.0f;
-            const float iE2 = iE * iE;
-            // sweep 2: weight adjoints, the centre-role terms and the sigma
-            // partials (the taps' weights recomputed with the same arithmetic)
-#pragma unroll 1
-            for (int b = -2; b <= 2; ++b)
-#pragma unroll
-            for (int a = -2; a <= 2; ++a) {
-                if (a == 0 && b == 0) continue;
-                const int e = c + b * CW + s * a;
-                const float4 nq = s_nz[e];
-                const float2 c2 = s_cv[e];
-                // fused_weight / depth_coef written out (the same bits as in
-                // sweep 1), its reciprocal and normal term reused below
+                if (b == 0 && a <= 0) continue;  // row 0: the taps right of the centre; their mirrors below
                 const float S = tap_span(dzp, a, b, s);
                 const float iF = hw_rcp(fmaf(sz, S, eps_zp));
-                const float xn = fminf(dot3(np, f3(nq)), 1.0f);
-                const float lx = hw_log2(xn);
-                const float ew = fmaf(kNegLog2e * iF, fabsf(n4.w - nq.w), fmaf(ke, fabsf(cvp.x - c2.x), sn * lx));
-                const float w = xn > 0.0f ? hw_exp2(ew) : 0.0f;
+                const float kz = kNegLog2e * iF, fz = S * iF * iF;
                 const float h = b3(a) * b3(b);
-                const float wbar = h * (A * (c2.x - cpr) - K2) + 2.0f * Bc * h * h * w * c2.y;
-                const float dc = cvp.x - c2.x;
-                const float ww = wbar * w;
-                cbar_c -= ww * sgn(dc) * iE;
-                gbar = fmaf(ww * fabsf(dc), sl * iE2, gbar);
-                s_l = fmaf(ww * fabsf(dc), g * iE2, s_l);
-                s_z = fmaf(ww * fabsf(n4.w - nq.w), S * iF * iF, s_z);
-                if (w > 0.0f && xn > 0.0f) s_n = fmaf(ww, lx * 0.6931471805599453f, s_n);
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const int e = m ? c - b * CW - s * a : c + b * CW + s * a;
+                    const float4 nq = s_nz[e];
+                    const float2 c2 = s_cv[e];
+                    const float xn = fminf(dot3(np, f3(nq)), 1.0f);
+                    const float lx = hw_log2(xn);
+                    const float adz = fabsf(n4.w - nq.w);
+                    const float dc = cvp.x - c2.x;
+                    const float ew = fmaf(kz, adz, fmaf(ke, fabsf(dc), sn * lx));
+                    const float w = xn > 0.0f ? hw_exp2(ew) : 0.0f;
+                    const float be = h * w, al = -be * dc, ga = be * be * c2.y;
+                    Dn += be;
+                    Sc += al;
+                    Sv += ga;
+                    const float phi[4] = {sgn(dc), fabsf(dc), adz * fz, w > 0.0f && xn > 0.0f ? lx : 0.0f};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        pa[k] = fmaf(al, phi[k], pa[k]);
+                        pb[k] = fmaf(be, phi[k], pb[k]);
+                        pg[k] = fmaf(ga, phi[k], pg[k]);
+                    }
+                }
             }
+            const float iD = 1.0f / Dn;
+            const float dlt = Sc * iD, cpr = cvp.x + dlt, vpr = Sv * iD * iD;
+            const float A = ab * iD, Bc = bb * iD * iD;
+            const float K2 = 2.0f * Bc * vpr * Dn;
+            const float mu = fmaf(A, dlt, K2), B2 = 2.0f * Bc;
+            float sum[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sum[k] = fmaf(A, pa[k], fmaf(-mu, pb[k], B2 * pg[k]));
+            const float iE2 = iE * iE;
+            const float cbar_c = -sum[0] * iE;
+            const float gbar = sum[1] * (sl * iE2);
+            s_l += sum[1] * (g * iE2);
+            s_z += sum[2];
+            s_n += sum[3] * 0.6931471805599453f;
             const float Gb = g > 0.0f ? gbar / (2.0f * g) / sk : 0.0f;
             D.coef[i] = make_float4(A, Bc, cpr, iE);
             D.aux[i] = make_float4(Gb, cbar_c, K2, 0.0f);
