@@ -57,15 +57,28 @@ __global__ __launch_bounds__(kB) void bounds_kernel(const float* __restrict__ tr
     if (threadIdx.x < 7) partial[7 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// One workgroup of kB lanes: lane t folds partials t, t + kB, ... (all
+// seven components), then a tree over the lanes in LDS.  Min and max are
+// exact, so the result does not depend on the order.
 __global__ __launch_bounds__(kB) void bounds_final_kernel(float* partial, uint32_t nb) {
-    if (threadIdx.x >= 7) return;
-    const int k = threadIdx.x;
-    float v = partial[k];
-    for (uint32_t b = 1; b < nb; ++b) {
-        const float o = partial[7 * b + k];
-        v = (k < 3) ? fminf(v, o) : fmaxf(v, o);
+    __shared__ float red[7][kB];
+    float v[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0f};
+    for (uint32_t b = threadIdx.x; b < nb; b += kB)
+        for (int k = 0; k < 7; ++k) {
+            const float o = partial[7 * b + k];
+            v[k] = (k < 3) ? fminf(v[k], o) : fmaxf(v[k], o);
+        }
+    for (int k = 0; k < 7; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int h = kB / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 7; ++k) {
+                const float o = red[k][threadIdx.x + h];
+                red[k][threadIdx.x] = (k < 3) ? fminf(red[k][threadIdx.x], o) : fmaxf(red[k][threadIdx.x], o);
+            }
+        __syncthreads();
     }
-    partial[k] = v;  // the result lands in partial[0..6]
+    if (threadIdx.x < 7) partial[threadIdx.x] = red[threadIdx.x][0];  // the result lands in partial[0..6]
 }
 
 // ---- Morton codes of the centroids, 10 bits per axis ----
@@ -257,7 +270,7 @@ dhr_status fill(dhr_ctx* ctx, dhr_bvh* b, const float* tris, const uint32_t* obj
     const uint32_t T = b->n_tris;
     const uint32_t nb = std::min<uint32_t>(blocks(T), 1024);
     hipLaunchKernelGGL(bounds_kernel, dim3(nb), dim3(kB), 0, s, tris, T, b->bounds);
-    hipLaunchKernelGGL(bounds_final_kernel, dim3(1), dim3(64), 0, s, b->bounds, nb);
+    hipLaunchKernelGGL(bounds_final_kernel, dim3(1), dim3(kB), 0, s, b->bounds, nb);
     if (T == 1) {
         hipLaunchKernelGGL(leaves_kernel, dim3(1), dim3(kB), 0, s, tris, obj, order, T, b->tris, b->box, b->rec_of);
         hipLaunchKernelGGL(single_root_kernel, dim3(1), dim3(1), 0, s, tris, b->bounds, b->nodes);
@@ -331,7 +344,7 @@ dhr_status dhr_build_bvh_device(dhr_ctx* ctx, const float* tris, const uint32_t*
     dhr_status st = DHR_OK;
     const uint32_t nb = std::min<uint32_t>(blocks(T), 1024);
     hipLaunchKernelGGL(bounds_kernel, dim3(nb), dim3(kB), 0, s, tris, T, b->bounds);
-    hipLaunchKernelGGL(bounds_final_kernel, dim3(1), dim3(64), 0, s, b->bounds, nb);
+    hipLaunchKernelGGL(bounds_final_kernel, dim3(1), dim3(kB), 0, s, b->bounds, nb);
     if (T > 1) {
         hipLaunchKernelGGL(morton_kernel, dim3(blocks(T)), dim3(kB), 0, s, tris, T, b->bounds, key, val);
         if (hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, key, key2, val, order, (int)T, 0, 30, s) != hipSuccess)

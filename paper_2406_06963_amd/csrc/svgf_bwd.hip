@@ -544,6 +544,10 @@ __global__ __launch_bounds__(kReduceBlock) void sigma_reduce_kernel(const BwdBat
     }
 }
 
+__global__ void zero_kernel(float* p, uint32_t n) {
+    for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) p[k] = 0.0f;
+}
+
 void launch_adjoint_rows(uint32_t level, dim3 grid, hipStream_t s, const BwdBatch& B, const SvgfK& K) {
     switch (level) {
         case 0:
@@ -634,9 +638,9 @@ dhr_status dhr_svgf_backward(dhr_ctx* ctx, const dhr_svgf_params* params, const 
     }();
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (n_frames == 0) {
-        if (hipMemsetAsync(grad_sigma, 0, sizeof(float) * 3 * L, s) != hipSuccess)
-            return set_error(ctx, DHR_ERR_DEVICE, "dhr_svgf_backward: memset failed");
-        return DHR_OK;
+        // a fill kernel rather than a memset node, so the call can be captured in a graph
+        hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, grad_sigma, 3 * L);
+        return check_launch(ctx, "dhr_svgf_backward");
     }
     for (size_t b0 = 0; b0 < descs.size(); b0 += kBwdMaxB) {
         BwdBatch B;

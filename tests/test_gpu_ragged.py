@@ -127,3 +127,16 @@ def test_spatial_and_adjoint_ragged(B, ctx, preset, levels):
         assert rel <= 1e-3
     gs = gs.cpu().numpy().reshape(3, levels)
     assert (np.abs(gs - gs_o) <= 1e-3 * np.abs(gs_o) + 1e-6).all(), (gs, gs_o)
+
+
+def test_empty_batches(B, ctx):
+    """Zero frames: the filter and the spatial forward launch nothing and
+    succeed; the adjoint's sigma gradient is the empty sum, zero."""
+    import torch
+    P = B.svgf_params()
+    B.dhr_svgf_filter(ctx, P, [])
+    B.dhr_svgf_spatial_forward(ctx, P, [])
+    gs = torch.full((3 * P.levels,), 7.0, device="cuda")
+    B.dhr_svgf_backward(ctx, P, [], gs)
+    torch.cuda.synchronize()
+    assert bool((gs == 0.0).all())
