@@ -756,11 +756,13 @@ def bench_serving(B, ctx, args):
             server.disconnect(sp.client_id)
     res["speedup_frames_per_s"] = res["batched"]["frames_per_s"] / max(res["per_client"]["frames_per_s"], 1e-9)
     # capacity: every client always has a fresh request (rate far above what
-    # the device can serve), batched vs per-client plain launches
-    sat = sv.request_trace(specs, min(args.serve_seconds, 3.0), rate_hz=400.0, max_delay_s=0.0)
+    # the device can serve), still with the U[0, 200] ms delays and the
+    # staleness limit, batched vs per-client plain launches
+    sat = sv.request_trace(specs, min(args.serve_seconds, 3.0), rate_hz=400.0, max_delay_s=0.2)
+    res["saturated_requests"] = len(sat)
     for mode, kw in modes:
         ex = sv.GpuExecutor(ctx, scenes, n_streams=kw["max_inflight"])
-        server = sv.Server(ex, budget_bytes=200e9, max_stale_s=10.0, **kw)
+        server = sv.Server(ex, budget_bytes=200e9, **kw)
         for sp in specs:
             server.connect(sp)
         wall = sv.run_trace(server, sat, min(args.serve_seconds, 3.0))

@@ -349,13 +349,7 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, c
     stage_tile<TW * TW>(
         [&](int e) {
             const int qx = bx + s * (e % TW - KR), qy = by + s * (e / TW - KR);
-            Staged r{make_float4(0.0f, 0.0f, 0.0f, 0.0f), make_float2(0.0f, 0.0f)};
-            if (qx >= 0 && qx < W && qy >= 0 && qy < H) {
-                const size_t q = (size_t)qy * W + qx;
-                r.nz = D.nz[q];
-                r.cv = src[q];
-            }
-            return r;
+            return load_staged(D.nz, src, qx, qy, W, H);
         },
         [&](int e, const Staged& r) {
             const bool ok = r.nz.w > 0.0f;
@@ -388,10 +382,9 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_kernel(const SvgfBatch B, c
 #pragma unroll
             for (int a = -1; a <= 1; ++a) {
                 const int e = c + b * TW + a;
-                if (!(s_nz[e].w > 0.0f)) continue;
                 const float k = k3(a) * k3(b);
-                G = fmaf(k, s_cv[e].y, G);
-                sk += k;
+                G = fmaf(k, s_cv[e].y, G);  // zero on invalid pixels
+                sk += s_nz[e].w > 0.0f ? k : 0.0f;
             }
         ke = ke_of(G, sk, P.sl[LEVEL], P.eps_l);
     } else {
@@ -453,13 +446,7 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_rows_kernel(const SvgfBatch
     stage_tile<CH * CW>(
         [&](int e) {
             const int qx = x0 - KR * s + e % CW, qy = y0 + s * (e / CW - KR);
-            Staged r{make_float4(0.0f, 0.0f, 0.0f, 0.0f), make_float2(0.0f, 0.0f)};
-            if (qx >= 0 && qx < W && qy >= 0 && qy < H) {
-                const size_t q = (size_t)qy * W + qx;
-                r.nz = D.nz[q];
-                r.cv = src[q];
-            }
-            return r;
+            return load_staged(D.nz, src, qx, qy, W, H);
         },
         [&](int e, const Staged& r) {
             const bool ok = r.nz.w > 0.0f;
@@ -471,7 +458,8 @@ __global__ __launch_bounds__(kSvgfBlock) void atrous_rows_kernel(const SvgfBatch
     stage_tile<kRowsTY * 2 * GW>(
         [&](int e) {
             const int qx = x0 - 1 + e % GW, qy = y0 + s * (e / (2 * GW)) + ((e / GW) % 2 ? 1 : -1);
-            return (qx >= 0 && qx < W && qy >= 0 && qy < H) ? src[(size_t)qy * W + qx].y : kNoVar;
+            const float v = src[clamped_index(qx, qy, W, H)].y;
+            return inside(qx, qy, W, H) ? v : kNoVar;
         },
         [&](int e, float v) { s_g[e] = v; });
     __syncthreads();

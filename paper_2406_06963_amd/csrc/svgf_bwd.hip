@@ -263,13 +263,7 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_a_rows(const BwdBatch Bt, 
     stage_tile<CH * CW>(
         [&](int e) {
             const int qx = x0 - 2 * s + e % CW, qy = y0 + s * (e / CW - 2);
-            Staged r{make_float4(0.0f, 0.0f, 0.0f, 0.0f), make_float2(0.0f, 0.0f)};
-            if (qx >= 0 && qx < W && qy >= 0 && qy < H) {
-                const size_t q = (size_t)qy * W + qx;
-                r.nz = D.nz[q];
-                r.cv = cv[q];
-            }
-            return r;
+            return load_staged(D.nz, cv, qx, qy, W, H);
         },
         [&](int e, const Staged& r) {
             const bool ok = r.nz.w > 0.0f;
@@ -279,13 +273,9 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_a_rows(const BwdBatch Bt, 
     stage_tile<kRowsTY * 2 * GW>(
         [&](int e) {
             const int qx = x0 - 1 + e % GW, qy = y0 + s * (e / (2 * GW)) + ((e / GW) % 2 ? 1 : -1);
-            float v = kNoVar;
-            if (qx >= 0 && qx < W && qy >= 0 && qy < H) {
-                const size_t q = (size_t)qy * W + qx;
-                const float vq = cv[q].y;
-                if (D.nz[q].w > 0.0f) v = vq;
-            }
-            return v;
+            const size_t q = clamped_index(qx, qy, W, H);
+            const float vq = cv[q].y;
+            return inside(qx, qy, W, H) && D.nz[q].w > 0.0f ? vq : kNoVar;
         },
         [&](int e, float v) { s_g[e] = v; });
     __syncthreads();
@@ -436,16 +426,13 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_b_rows(const BwdBatch Bt, 
     const float2* cv = D.save + (size_t)LEVEL * W * H;
     stage_tile<CH * CW>(
         [&](int e) {
+            // outside the frame: the nearest pixel's records, marked invalid
+            // (depth 0), which the store replaces by the neutral ones
             const int px = x0 - 2 * s + e % CW, py = y0 + s * (e / CW - 2);
-            StagedP r{make_float4(0.0f, 0.0f, 0.0f, 0.0f), make_float4(0.0f, 0.0f, 0.0f, 1.0f),
-                      make_float4(0.0f, 0.0f, 0.0f, 0.0f)};
-            if (px >= 0 && px < W && py >= 0 && py < H) {
-                const size_t p = (size_t)py * W + px;
-                r.nz = D.nz[p];
-                r.cf = D.coef[p];
-                const float2 dz = D.dz[p];
-                r.ck = make_float4(cv[p].x, D.aux[p].z, dz.x, dz.y);
-            }
+            const size_t p = clamped_index(px, py, W, H);
+            const float2 dz = D.dz[p];
+            StagedP r{D.nz[p], D.coef[p], make_float4(cv[p].x, D.aux[p].z, dz.x, dz.y)};
+            if (!inside(px, py, W, H)) r.nz.w = 0.0f;
             return r;
         },
         [&](int e, const StagedP& r) {
@@ -457,7 +444,8 @@ __global__ __launch_bounds__(kSvgfBlock) void adjoint_b_rows(const BwdBatch Bt, 
     stage_tile<kRowsTY * 3 * GW>(
         [&](int e) {
             const int rx = x0 - 1 + e % GW, ry = y0 + s * (e / (3 * GW)) + (e / GW) % 3 - 1;
-            return (rx >= 0 && rx < W && ry >= 0 && ry < H) ? D.aux[(size_t)ry * W + rx].x : 0.0f;
+            const float v = D.aux[clamped_index(rx, ry, W, H)].x;
+            return inside(rx, ry, W, H) ? v : 0.0f;
         },
         [&](int e, float v) { s_gb[e] = v; });
     __syncthreads();

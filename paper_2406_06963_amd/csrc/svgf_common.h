@@ -59,7 +59,7 @@ __device__ __forceinline__ bool has_var(float v) { return v > -1.0e38f; }
 // ke = -log2(e) / (sigma_l g + eps_l) with g = sqrt of the 3x3 (1,2,1)/4 blur of
 // the variance over valid pixels (G and its weight sk accumulated by the caller)
 __device__ __forceinline__ float ke_of(float G, float sk, float sl, float eps_l) {
-    return -1.4426950408889634f / fmaf(sl, sqrtf(G / sk), eps_l);
+    return -1.4426950408889634f * __builtin_amdgcn_rcpf(fmaf(sl, __builtin_amdgcn_sqrtf(G * __builtin_amdgcn_rcpf(sk)), eps_l));
 }
 
 __device__ __forceinline__ void tile_xy(uint32_t t, uint32_t tiles_x, uint32_t& x, uint32_t& y) {
@@ -110,6 +110,28 @@ struct Staged {
     float4 nz;
     float2 cv;
 };
+
+__device__ __forceinline__ bool inside(int qx, int qy, int W, int H) {
+    return (unsigned)qx < (unsigned)W && (unsigned)qy < (unsigned)H;
+}
+
+// Index of the pixel nearest to (qx, qy) inside the frame: staging loads
+// read it unconditionally (no branch per staged pixel) and discard what lies
+// outside.
+__device__ __forceinline__ size_t clamped_index(int qx, int qy, int W, int H) {
+    return (size_t)min(max(qy, 0), H - 1) * (size_t)W + (size_t)min(max(qx, 0), W - 1);
+}
+
+// A staged pixel's geometry and (c, var); outside the frame it reads its
+// nearest pixel and reports depth 0 (invalid), which the staging stores as a
+// zero normal.
+__device__ __forceinline__ Staged load_staged(const float4* __restrict__ nz, const float2* __restrict__ cv, int qx,
+                                              int qy, int W, int H) {
+    const size_t q = clamped_index(qx, qy, W, H);
+    Staged r{nz[q], cv[q]};
+    if (!inside(qx, qy, W, H)) r.nz.w = 0.0f;
+    return r;
+}
 
 // Workgroups are dispatched to the 8 XCDs round-robin by id.  This remap
 // (a bijection of [0, nb)) makes consecutive logical tiles share an XCD, so
