@@ -102,6 +102,11 @@ def parse():
     return ap.parse_args()
 
 
+def progress(msg: str) -> None:
+    """A progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def svgf_bytes_per_px(levels: int) -> int:
     """Algorithmic bytes of the filter per pixel: each pass reads its inputs
     and writes its outputs once (neighbourhoods from cache).
@@ -169,6 +174,7 @@ def main():
     tps = [tparams(f) for f in range(nfr)]
     w0, w1 = args.warmup, args.warmup + args.steps
 
+    progress(f"{pr.name}: scene and BVH ready ({bvh_s:.2f} s); timed steps")
     pipe.run(cams, tps, 0, w0)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -327,6 +333,7 @@ def main():
         line["svgf_ao_and_shadow"] = {"ms": two_ms, "mpix_s": 2 * HW / (two_ms / 1e3) / 1e6,
                                       "vs_ao_only": two_ms / per["svgf_seq"]}
 
+    progress(f"step {ms_per_step:.4f} ms; filter levels and batch")
     line["svgf_levels"] = bench_svgf_levels(B, ctx, W, H, P, gb[f_end % 2], out_s)
     line["svgf_batch4"] = bench_svgf_batch(B, ctx, bvh, pr, cams, lights, P, f_end, 4)
 
@@ -337,6 +344,7 @@ def main():
     if len(lf) >= 3:
         line["svgf_light"] = bench_light_filter(B, ctx, bvh, pr, cams, lights, gb, ao, sh, P, lf)
 
+    progress("device BVH, instancing, rasterised G-buffer, wire form")
     # the hierarchy built on the device (linear BVH) and refitted, and the
     # ray passes on it, against the host SAH build used above
     tri_d = torch.from_numpy(np.ascontiguousarray(scene.tris, dtype=np.float32).reshape(-1, 9)).to(dev)
@@ -420,13 +428,16 @@ def main():
     line["encode"] = {"us": enc_s * 1e6, "bytes_per_px": 4 + len(lights) + 2,
                       "roofline": {"bound": "hbm", "achieved": enc_bytes / enc_s / 1e9, "peak": HBM_PEAK_GBS,
                                    "unit": "GB/s", "frac": enc_bytes / enc_s / 1e9 / HBM_PEAK_GBS}}
+    progress("other workloads, differentiation, serving, CPU baseline")
     if args.other_steps > 0:
         line["other_workloads"] = {name: bench_preset(B, ctx, name, args.other_steps) for name in ("tiny", "room720")}
     if args.bwd_frames > 0:
         line["differentiation"] = bench_backward(B, ctx, args.bwd_frames)
+        progress("differentiation done")
     if args.serve_seconds > 0:
         line["serving"] = bench_serving(B, ctx, args)
         line["p99_ms"] = line["serving"]["continuous"]["p99_ms"]
+        progress("serving done")
     if args.cpu_frames > 0:
         line["cpu_baseline"] = cpu_baseline(pr, scene, cams, lights, args)
     print(json.dumps(line), flush=True)
@@ -750,6 +761,7 @@ def bench_serving(B, ctx, args):
              ("continuous_fused", dict(max_batch=4, max_inflight=8)),
              ("plain", dict(max_batch=1, max_inflight=1)))
     for mode, kw in modes:
+        progress(f"serving: {mode} at 30 Hz")
         ex = sv.GpuExecutor(ctx, scenes, n_streams=kw["max_inflight"])
         server = sv.Server(ex, budget_bytes=200e9, **kw)
         for sp in specs:
@@ -765,6 +777,7 @@ def bench_serving(B, ctx, args):
     sat_s = min(args.serve_seconds, 3.0)
     sat = sv.request_trace(specs, sat_s, rate_hz=400.0, max_delay_s=0.0)
     for mode, kw in modes:
+        progress(f"serving: {mode} at saturation")
         ex = sv.GpuExecutor(ctx, scenes, n_streams=kw["max_inflight"])
         server = sv.Server(ex, budget_bytes=200e9, **kw)
         for sp in specs:
