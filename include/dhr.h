@@ -65,7 +65,12 @@ typedef void* dhr_stream; /* hipStream_t */
 
 /* Creates a context bound to HIP device `device`.  *out receives the handle
  * (library-owned; free with dhr_destroy).  DHR_ERR_DEVICE if the device is
- * absent, DHR_ERR_UNSUPPORTED if it is not gfx950. */
+ * absent, DHR_ERR_UNSUPPORTED if it is not gfx950.
+ * Traversal addresses a single-level tree's records by 32-bit byte offsets
+ * when its node and triangle counts are both at most 2^26, by 64-bit offsets
+ * otherwise; the environment variable DHR_WIDE_RECORDS=1, read here, makes
+ * this context use 64-bit offsets for every tree (same results, for
+ * testing that path on small scenes). */
 dhr_status dhr_create(int device, dhr_ctx** out);
 void dhr_destroy(dhr_ctx* ctx);
 /* Message of the last failing call on this context ("" if none).  The string

@@ -1,4 +1,5 @@
 // Context, error reporting and parameter helpers of the C ABI.
+#include <cstdlib>
 #include <cstring>
 
 #include "internal.h"
@@ -42,6 +43,8 @@ dhr_status dhr_create(int device, dhr_ctx** out) {
     dhr_ctx* c = new dhr_ctx;
     c->device = device;
     c->n_cu = prop.multiProcessorCount;
+    const char* wide = std::getenv("DHR_WIDE_RECORDS");
+    c->wide_records = wide && wide[0] == '1';
     const dhr_status st = dhr::svgf_scratch_init(c);
     if (st != DHR_OK) {
         std::fprintf(stderr, "%s\n", c->err.c_str());

@@ -139,9 +139,24 @@ __device__ __forceinline__ float4 ld_const(const float4* base, int i) {
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// Record addressing.  Narrow (WIDE = false): the record's byte offset as a
+// 32-bit value, which the scalar load takes as its SGPR offset, so a node
+// step spends one shift instead of 64-bit address arithmetic on the scalar
+// unit (the walk's other bottleneck beside VALU issue).  It needs each array
+// under 4 GB: trees_narrow() on the host.  Wide: 64-bit offsets, any size.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* at_byte(const float4* base, uint32_t off) {
+    return (const __attribute__((address_space(4))) T*)((const __attribute__((address_space(4))) char*)base + off);
+}
+__device__ __forceinline__ float4 f4of(vf4 v) { return make_float4(v.x, v.y, v.z, v.w); }
+
+template <bool WIDE>
 __device__ __forceinline__ NodeRec load_node_uniform(const float4* __restrict__ nodes, int node) {
-    return NodeRec{ld_const(nodes, 4 * node), ld_const(nodes, 4 * node + 1), ld_const(nodes, 4 * node + 2),
-                   ld_const(nodes, 4 * node + 3)};
+    if (WIDE)
+        return NodeRec{ld_const(nodes, 4 * node), ld_const(nodes, 4 * node + 1), ld_const(nodes, 4 * node + 2),
+                       ld_const(nodes, 4 * node + 3)};
+    const __attribute__((address_space(4))) vf4* p = at_byte<vf4>(nodes, (uint32_t)node << 6);
+    return NodeRec{f4of(p[0]), f4of(p[1]), f4of(p[2]), f4of(p[3])};
 }
 
 // Slab test of both child boxes of a node against [0, tmax]: per axis the
@@ -226,8 +241,11 @@ __device__ __forceinline__ float tri_t_uniform(const float4* __restrict__ tris, 
 struct TriRec {
     float4 v0, e1, e2;
 };
+template <bool WIDE>
 __device__ __forceinline__ TriRec load_tri_uniform(const float4* __restrict__ tris, int i) {
-    return TriRec{ld_const(tris, 3 * i), ld_const(tris, 3 * i + 1), ld_const(tris, 3 * i + 2)};
+    if (WIDE) return TriRec{ld_const(tris, 3 * i), ld_const(tris, 3 * i + 1), ld_const(tris, 3 * i + 2)};
+    const __attribute__((address_space(4))) vf4* p = at_byte<vf4>(tris, (uint32_t)i * 48u);
+    return TriRec{f4of(p[0]), f4of(p[1]), f4of(p[2])};
 }
 
 // Whether the ray hits triangle (v0, e1, e2) at 0 < t < tmax: the
@@ -248,18 +266,22 @@ __device__ __forceinline__ bool tri_hits_rec(const TriRec& r, float3 o, float3 d
     return (U >= 0.0f) & (V >= 0.0f) & (U + V <= ad) & (T > 0.0f) & (T < tmax * ad);
 }
 
+template <bool WIDE>
 __device__ __forceinline__ bool tri_hits_uniform(const float4* __restrict__ tris, int i, float3 o, float3 d,
                                                  float tmax) {
-    return tri_hits_rec(load_tri_uniform(tris, i), o, d, tmax);
+    return tri_hits_rec(load_tri_uniform<WIDE>(tris, i), o, d, tmax);
 }
 
 // Two consecutive records i, i + 1 (96 bytes) as one 64- and one 32-byte
 // scalar load, so both are in flight before either is tested.
 typedef float vf16 __attribute__((ext_vector_type(16)));
 typedef float vf8 __attribute__((ext_vector_type(8)));
+template <bool WIDE>
 __device__ __forceinline__ void load_tri_pair_uniform(const float4* __restrict__ tris, int i, TriRec& a, TriRec& b) {
-    const vf16 p = *(const __attribute__((address_space(4))) vf16*)(tris + 3 * i);
-    const vf8 q = *(const __attribute__((address_space(4))) vf8*)(tris + 3 * i + 4);
+    const vf16 p = WIDE ? *(const __attribute__((address_space(4))) vf16*)(tris + 3 * i)
+                        : *at_byte<vf16>(tris, (uint32_t)i * 48u);
+    const vf8 q = WIDE ? *(const __attribute__((address_space(4))) vf8*)(tris + 3 * i + 4)
+                       : *at_byte<vf8>(tris, (uint32_t)i * 48u + 64u);
     a = TriRec{make_float4(p[0], p[1], p[2], p[3]), make_float4(p[4], p[5], p[6], p[7]),
                make_float4(p[8], p[9], p[10], p[11])};
     b = TriRec{make_float4(p[12], p[13], p[14], p[15]), make_float4(q[0], q[1], q[2], q[3]),
@@ -271,16 +293,16 @@ __device__ __forceinline__ void load_tri_pair_uniform(const float4* __restrict__
 // instead of one per triangle; an odd last triangle is loaded alone (the
 // record after it may lie beyond the array).  test(rec, index) is called in
 // index order.
-template <class Test>
+template <bool WIDE, class Test>
 __device__ __forceinline__ void leaf_pairs(const float4* __restrict__ tris, int first, int count, Test test) {
     int k = 0;
     for (; k + 1 < count; k += 2) {
         TriRec a, b;
-        load_tri_pair_uniform(tris, first + k, a, b);
+        load_tri_pair_uniform<WIDE>(tris, first + k, a, b);
         test(a, first + k);
         test(b, first + k + 1);
     }
-    if (k < count) test(load_tri_uniform(tris, first + k), first + k);
+    if (k < count) test(load_tri_uniform<WIDE>(tris, first + k), first + k);
 }
 
 __device__ __forceinline__ void leaf_range(int ref, int& first, int& count) {
@@ -315,7 +337,7 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // With COUNT, `cnt` tallies the work of this lane's own ray: the nodes and
 // leaves whose boxes it hits (a bit stack beside the wave's stack records
 // whether it hit each pushed child) and the triangles of those leaves.
-template <bool COUNT, int OCT, class Leaf, class Done>
+template <bool COUNT, int OCT, bool WIDE, class Leaf, class Done>
 __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, float3 id, float3 ood,
                                             const float& tmax, bool live, int* wstk, Leaf visit_leaf, Done done,
                                             TravCount* cnt) {
@@ -327,7 +349,7 @@ __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, fl
             float t0, x0, t1, x1;
             int c0, c1;
             if (COUNT && in) ++cnt->nodes;
-            box_test<OCT>(load_node_uniform(nodes, node), id, ood, t0, x0, t1, x1, c0, c1);
+            box_test<OCT>(load_node_uniform<WIDE>(nodes, node), id, ood, t0, x0, t1, x1, c0, c1);
             c0 = uniform(c0);
             c1 = uniform(c1);
             // hit masks: entry <= exit and entry <= tmax, each compare's own lane
@@ -372,24 +394,24 @@ __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, fl
 // packet_walk with the box test specialised for the wave's direction signs
 // when the live lanes share them (shadow rays towards one light, most
 // primary-ray waves), the generic one otherwise (ambient-occlusion rays).
-template <bool COUNT, class Leaf, class Done>
+template <bool COUNT, bool WIDE, class Leaf, class Done>
 __device__ __forceinline__ void walk(const float4* __restrict__ nodes, float3 id, float3 ood, const float& tmax,
                                      bool live, int* wstk, Leaf leaf, Done done, TravCount* cnt) {
     switch (wave_octant(id, live)) {
-        case 0: packet_walk<COUNT, 0>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
-        case 1: packet_walk<COUNT, 1>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
-        case 2: packet_walk<COUNT, 2>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
-        case 3: packet_walk<COUNT, 3>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
-        case 4: packet_walk<COUNT, 4>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
-        case 5: packet_walk<COUNT, 5>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
-        case 6: packet_walk<COUNT, 6>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
-        case 7: packet_walk<COUNT, 7>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
-        default: packet_walk<COUNT, -1>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        case 0: packet_walk<COUNT, 0, WIDE>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        case 1: packet_walk<COUNT, 1, WIDE>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        case 2: packet_walk<COUNT, 2, WIDE>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        case 3: packet_walk<COUNT, 3, WIDE>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        case 4: packet_walk<COUNT, 4, WIDE>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        case 5: packet_walk<COUNT, 5, WIDE>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        case 6: packet_walk<COUNT, 6, WIDE>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        case 7: packet_walk<COUNT, 7, WIDE>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
+        default: packet_walk<COUNT, -1, WIDE>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt); break;
     }
 }
 
 // Any hit at 0 < t < r.tmax for the lanes with `live`; the others return false.
-template <bool COUNT = false>
+template <bool COUNT, bool WIDE>
 __device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const float4* __restrict__ tris, const Ray& r,
                                         bool live, int* wstk, TravCount* cnt = nullptr) {
     if (!__any(live)) return false;
@@ -401,21 +423,21 @@ __device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const 
     // measured slower on the visibility rays)
     auto leaf = [&](int first, int count) {
         for (int k = 0; k < count; ++k) {
-            if (tri_hits_uniform(tris, first + k, r.o, r.d, tmax)) {  // false for finished lanes (tmax < 0)
+            if (tri_hits_uniform<WIDE>(tris, first + k, r.o, r.d, tmax)) {  // false for finished lanes (tmax < 0)
                 hit = true;
                 tmax = -1.0f;
             }
         }
     };
     auto done = [&] { return !__any(tmax >= 0.0f); };
-    walk<COUNT>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt);
+    walk<COUNT, WIDE>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt);
     return hit;
 }
 
 // Closest hit at t > 0 (ties: lowest original triangle index) for the lanes
 // with `live`; returns the position in leaf order, or -1.  COUNT: as for
 // any_hit.
-template <bool COUNT = false>
+template <bool COUNT, bool WIDE>
 __device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, const float4* __restrict__ tris, float3 o,
                                            float3 d, bool live, float& tbest, int* wstk, TravCount* cnt = nullptr) {
     const float3 id = safe_inv(d);
@@ -424,7 +446,7 @@ __device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, con
     uint32_t best_orig = 0xFFFFFFFFu;
     tbest = live ? __builtin_inff() : -1.0f;
     auto leaf = [&](int first, int count) {
-        leaf_pairs(tris, first, count, [&](const TriRec& rec, int k) {
+        leaf_pairs<WIDE>(tris, first, count, [&](const TriRec& rec, int k) {
             const uint32_t orig = fbits(rec.v0.w);
             const float t = tri_t_rec(rec.v0, rec.e1, rec.e2, o, d);
             if (t > 0.0f && t <= tbest && (t < tbest || orig < best_orig)) {
@@ -435,7 +457,7 @@ __device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, con
         });
     };
     auto done = [] { return false; };
-    walk<COUNT>(nodes, id, ood, tbest, live, wstk, leaf, done, cnt);
+    walk<COUNT, WIDE>(nodes, id, ood, tbest, live, wstk, leaf, done, cnt);
     if (!live) tbest = __builtin_inff();
     return best;
 }
@@ -471,14 +493,15 @@ __device__ __forceinline__ float3 xf_dir(float4 r0, float4 r1, float4 r2, float3
 }
 
 // Walks bottom level b for the ray (o, d) in its space; `leaf(first, count)`
-// as in packet_walk.  The live lanes are those with tmax >= 0.
+// as in packet_walk.  The live lanes are those with tmax >= 0.  Two-level
+// walks address records wide, whatever the size of their arrays.
 template <class Leaf, class Done>
 __device__ __forceinline__ void walk_bottom(const float4* __restrict__ nodes, float3 o, float3 d, const float& tmax,
                                             int* wstk, Leaf leaf, Done done) {
     const float3 id = safe_inv(d);
     const float3 ood = f3(o.x * id.x, o.y * id.y, o.z * id.z);
     const bool live = tmax >= 0.0f;
-    packet_walk<false, -1>(nodes, id, ood, tmax, live, wstk, leaf, done, nullptr);
+    packet_walk<false, -1, true>(nodes, id, ood, tmax, live, wstk, leaf, done, nullptr);
 }
 
 // any_hit through a two-level hierarchy (`top` its top-level nodes); wstk2
@@ -500,7 +523,7 @@ __device__ __forceinline__ bool any_hit_2l(const float4* __restrict__ top, const
             const float4* tb = bottom_tris(L, b);
             auto leaf = [&](int f, int c) {
                 for (int j = 0; j < c; ++j)
-                    if (tri_hits_uniform(tb, f + j, o, d, tmax)) {  // false for finished lanes
+                    if (tri_hits_uniform<true>(tb, f + j, o, d, tmax)) {  // false for finished lanes
                         hit = true;
                         tmax = -1.0f;
                     }
@@ -508,7 +531,7 @@ __device__ __forceinline__ bool any_hit_2l(const float4* __restrict__ top, const
             walk_bottom(bottom_nodes(L, b), o, d, tmax, wstk2, leaf, done);
         }
     };
-    packet_walk<false, -1>(top, id, ood, tmax, live, wstk, top_leaf, done, nullptr);
+    packet_walk<false, -1, true>(top, id, ood, tmax, live, wstk, top_leaf, done, nullptr);
     return hit;
 }
 
@@ -547,7 +570,7 @@ __device__ __forceinline__ void closest_hit_2l(const float4* __restrict__ top, c
             walk_bottom(bottom_nodes(L, b), oo, dd, tbest, wstk2, leaf, done);
         }
     };
-    packet_walk<false, -1>(top, id, ood, tbest, live, wstk, top_leaf, done, nullptr);
+    packet_walk<false, -1, true>(top, id, ood, tbest, live, wstk, top_leaf, done, nullptr);
     if (!live) tbest = __builtin_inff();
 }
 

@@ -17,6 +17,7 @@ struct dhr_ctx {
     std::string err;
     uint64_t* trace_counters = nullptr;  // instrumentation (dhr_set_trace_counters)
     void* scratch = nullptr;             // device address of this device's filter scratch (dhr_svgf_filter_noalloc)
+    bool wide_records = false;           // DHR_WIDE_RECORDS=1: 64-bit record addressing for every tree
 };
 
 // Device-resident BVH.  Node: 4 x 16 bytes (two child boxes + child refs);

@@ -139,7 +139,7 @@ struct TraceShared {
 // G-buffer texels p4, n4 (this lane's pixel (x, y), index i; `inside`
 // false for lanes beyond the image).  Every lane of the workgroup takes
 // part (barriers).  With COUNT, tc and n_rays tally this lane's work.
-template <bool COUNT, bool TWO_LEVEL>
+template <bool COUNT, bool TWO_LEVEL, bool WIDE>
 __device__ __forceinline__ void trace_block(const TraceDesc& D, uint32_t t, uint32_t x, uint32_t y, bool inside,
                                             size_t i, float4 p4, float4 n4, TraceShared<TWO_LEVEL>& S, TravCount& tc,
                                             uint32_t& n_rays) {
@@ -190,7 +190,7 @@ __device__ __forceinline__ void trace_block(const TraceDesc& D, uint32_t t, uint
             bool decided, occ;
             make_ray(D, st, s, px, py, f3(so), f3(sn), v, r, decided, occ);
             const bool h = TWO_LEVEL ? any_hit_2l(D.nodes, L, r, !decided, wstk, wstk2)
-                                     : any_hit<COUNT>(D.nodes, D.tris, r, !decided, wstk, &tc);
+                                     : any_hit<COUNT, WIDE>(D.nodes, D.tris, r, !decided, wstk, &tc);
             if (!decided) occ = h;
             if (COUNT && !decided) ++n_rays;
             if (!v || !occ) {
@@ -220,8 +220,10 @@ __device__ __forceinline__ void trace_block(const TraceDesc& D, uint32_t t, uint
 }
 
 // COUNT: the instrumented variant that also tallies rays, node visits, leaf
-// visits and triangle tests into `counters` (device uint64[4]).
-template <bool COUNT, bool TWO_LEVEL>
+// visits and triangle tests into `counters` (device uint64[4]).  WIDE: the
+// record addressing of single-level trees (device.h; two-level walks are
+// always wide).
+template <bool COUNT, bool TWO_LEVEL, bool WIDE>
 __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsigned long long* counters) {
     __shared__ TraceShared<TWO_LEVEL> S;
     const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsig
     const size_t i = inside ? (size_t)y * D.W + x : 0;
     TravCount tc;
     uint32_t n_rays = 0;
-    trace_block<COUNT, TWO_LEVEL>(D, t, x, y, inside, i, D.pos[i], D.nz[i], S, tc, n_rays);
+    trace_block<COUNT, TWO_LEVEL, WIDE>(D, t, x, y, inside, i, D.pos[i], D.nz[i], S, tc, n_rays);
     if (COUNT) {
         // one vector atomic per lane (instrumented runs only)
         atomicAdd(counters + 0, (unsigned long long)n_rays);
@@ -246,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsig
 // The G-buffer texel of pixel (x, y) of job D: the closest hit of the ray
 // through the pixel centre.  Lanes with live false (beyond the image) take
 // part in the walk without a ray.
-template <bool TWO_LEVEL, bool COUNT = false>
+template <bool TWO_LEVEL, bool WIDE, bool COUNT = false>
 __device__ __forceinline__ void texel_of(const GbufDesc& D, uint32_t x, uint32_t y, bool live, int* wstk, int* wstk2,
                                          float4& pos, float4& nz, float2& dz, float2& mv, TravCount* cnt = nullptr) {
     const CamD& C = D.cur;
@@ -254,7 +256,7 @@ __device__ __forceinline__ void texel_of(const GbufDesc& D, uint32_t x, uint32_t
     const float3 d = cam_dir(C, x + 0.5f, y + 0.5f);
     float t;
     if (!TWO_LEVEL) {
-        const int hit = closest_hit<COUNT>(D.nodes, D.tris, eye, d, live, t, wstk, cnt);
+        const int hit = closest_hit<COUNT, WIDE>(D.nodes, D.tris, eye, d, live, t, wstk, cnt);
         gbuffer_texel(C, D.prev, D.has_prev != 0, D.W, D.H, x, y, d, hit < 0 ? nullptr : D.tris + 3 * hit, t, pos,
                       nz, dz, mv);
         return;
@@ -278,7 +280,7 @@ __device__ __forceinline__ void texel_of(const GbufDesc& D, uint32_t x, uint32_t
     gbuffer_texel(C, D.prev, D.has_prev != 0, D.W, D.H, x, y, d, inst < 0 ? nullptr : rec, t, pos, nz, dz, mv);
 }
 
-template <bool TWO_LEVEL>
+template <bool TWO_LEVEL, bool WIDE>
 __global__ __launch_bounds__(kBlock) void gbuffer_kernel(const GbufBatch B) {
     __shared__ int stack[kStack * (kBlock / 64) * (TWO_LEVEL ? 2 : 1)];
     const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
@@ -288,7 +290,8 @@ __global__ __launch_bounds__(kBlock) void gbuffer_kernel(const GbufBatch B) {
     if (x >= D.W || y >= D.H) return;
     const size_t i = (size_t)y * D.W + x;
     int* wstk = stack + (threadIdx.x >> 6) * kStack;
-    texel_of<TWO_LEVEL>(D, x, y, true, wstk, wstk + (kBlock / 64) * kStack, D.pos[i], D.nz[i], D.dz[i], D.mv[i]);
+    texel_of<TWO_LEVEL, WIDE>(D, x, y, true, wstk, wstk + (kBlock / 64) * kStack, D.pos[i], D.nz[i], D.dz[i],
+                              D.mv[i]);
 }
 
 // G-buffer and visibility of a frame in one launch: each workgroup writes the
@@ -306,7 +309,7 @@ static_assert(sizeof(FrameBatch) <= 4000, "kernel arguments too large");
 
 // COUNT: the instrumented variant (single-level hierarchies), tallying the
 // primary and the visibility rays' work into `counters` as trace_kernel does.
-template <bool COUNT, bool TWO_LEVEL>
+template <bool COUNT, bool TWO_LEVEL, bool WIDE>
 __global__ __launch_bounds__(kBlock) void frame_kernel(const FrameBatch B, unsigned long long* counters) {
     __shared__ TraceShared<TWO_LEVEL> S;
     const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
@@ -321,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(const FrameBatch B, unsig
     float2 dz, mv;
     int* wstk = S.stack + w * kStack;
     TravCount tc;
-    texel_of<TWO_LEVEL, COUNT>(F.g, x, y, inside, wstk, TWO_LEVEL ? S.stack + (kBlock / 64 + w) * kStack : wstk, pos,
+    texel_of<TWO_LEVEL, WIDE, COUNT>(F.g, x, y, inside, wstk, TWO_LEVEL ? S.stack + (kBlock / 64 + w) * kStack : wstk, pos,
                                nz, dz, mv, &tc);
     if (inside) {
         F.g.pos[i] = pos;
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(const FrameBatch B, unsig
         F.g.mv[i] = mv;
     }
     uint32_t n_rays = inside ? 1 : 0;
-    trace_block<COUNT, TWO_LEVEL>(F.t, t, x, y, inside, i, pos, nz, S, tc, n_rays);
+    trace_block<COUNT, TWO_LEVEL, WIDE>(F.t, t, x, y, inside, i, pos, nz, S, tc, n_rays);
     if (COUNT) {
         atomicAdd(counters + 0, (unsigned long long)n_rays);
         atomicAdd(counters + 1, (unsigned long long)tc.nodes);
@@ -416,6 +419,29 @@ void fill_trace_desc(const dhr_bvh* bvh, const dhr_trace_params& p, const float*
 
 uint32_t tiles_of(uint32_t W, uint32_t H) { return ((W + kTileW - 1) / kTileW) * ((H + kTileH - 1) / kTileH); }
 
+// Launch group of a job's hierarchy: narrow-addressed single level, wide
+// single level (node or triangle array beyond 4 GB, or forced by the
+// context), two levels.
+enum Hier { kNarrow = 0, kWide = 1, kTwoLevel = 2 };
+Hier hier_of(const dhr_ctx* ctx, const dhr_bvh* b) {
+    if (b->tl) return kTwoLevel;
+    const bool fits = b->info.n_nodes <= (1ull << 26) && b->info.n_tris <= (1ull << 26);
+    return fits && !ctx->wide_records ? kNarrow : kWide;
+}
+
+// Splits jobs (descs[k], tiles[k], hierarchy h[k]) into the three groups.
+template <class D>
+struct Groups {
+    std::vector<D> d[3];
+    std::vector<uint32_t> t[3];
+    Groups(const std::vector<D>& descs, const std::vector<uint32_t>& tiles, const std::vector<Hier>& h) {
+        for (size_t k = 0; k < descs.size(); ++k) {
+            d[h[k]].push_back(descs[k]);
+            t[h[k]].push_back(tiles[k]);
+        }
+    }
+};
+
 template <class D, int MAXB, class K, class... Extra>
 dhr_status launch_batches(dhr_ctx* ctx, const std::vector<D>& descs, const std::vector<uint32_t>& tiles, K kernel,
                           int block, hipStream_t s, const char* what, Extra... extra) {
@@ -465,24 +491,28 @@ dhr_status trace_jobs(dhr_ctx* ctx, const dhr_trace_job* jobs, uint32_t n, const
         if (st != DHR_OK) return st;
         tiles[k] = tiles_of(jobs[k].params.W, jobs[k].params.H);
     }
+    std::vector<Hier> h(n);
+    for (uint32_t k = 0; k < n; ++k) h[k] = hier_of(ctx, jobs[k].bvh);
     DeviceGuard g(ctx->device);
     unsigned long long* cnt = reinterpret_cast<unsigned long long*>(ctx->trace_counters);
     // one launch sequence per hierarchy kind
-    std::vector<TraceDesc> d1, d2;
-    std::vector<uint32_t> t1, t2;
-    for (uint32_t k = 0; k < n; ++k) {
-        (descs[k].tl ? d2 : d1).push_back(descs[k]);
-        (descs[k].tl ? t2 : t1).push_back(tiles[k]);
-    }
-    if (cnt && !d2.empty())
+    const Groups<TraceDesc> G(descs, tiles, h);
+    if (cnt && !G.d[kTwoLevel].empty())
         return set_error(ctx, DHR_ERR_UNSUPPORTED, "%s: work counters cover single-level hierarchies only", what);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     dhr_status st = DHR_OK;
-    if (!d1.empty())
-        st = cnt ? launch_batches<TraceDesc, kTraceMaxB>(ctx, d1, t1, trace_kernel<true, false>, kBlock, s, what, cnt)
-                 : launch_batches<TraceDesc, kTraceMaxB>(ctx, d1, t1, trace_kernel<false, false>, kBlock, s, what, cnt);
-    if (st == DHR_OK && !d2.empty())
-        st = launch_batches<TraceDesc, kTraceMaxB>(ctx, d2, t2, trace_kernel<false, true>, kBlock, s, what, cnt);
+    auto go = [&](Hier k, auto kernel) {
+        if (st == DHR_OK && !G.d[k].empty())
+            st = launch_batches<TraceDesc, kTraceMaxB>(ctx, G.d[k], G.t[k], kernel, kBlock, s, what, cnt);
+    };
+    if (cnt) {
+        go(kNarrow, trace_kernel<true, false, false>);
+        go(kWide, trace_kernel<true, false, true>);
+    } else {
+        go(kNarrow, trace_kernel<false, false, false>);
+        go(kWide, trace_kernel<false, false, true>);
+    }
+    go(kTwoLevel, trace_kernel<false, true, true>);
     return st;
 }
 
@@ -518,18 +548,19 @@ dhr_status gbuffer_jobs(dhr_ctx* ctx, const dhr_gbuffer_job* jobs, uint32_t n, d
         if (st != DHR_OK) return st;
         tiles[k] = tiles_of(jobs[k].W, jobs[k].H);
     }
+    std::vector<Hier> h(n);
+    for (uint32_t k = 0; k < n; ++k) h[k] = hier_of(ctx, jobs[k].bvh);
     DeviceGuard g(ctx->device);
-    std::vector<GbufDesc> d1, d2;
-    std::vector<uint32_t> t1, t2;
-    for (uint32_t k = 0; k < n; ++k) {
-        (descs[k].tl ? d2 : d1).push_back(descs[k]);
-        (descs[k].tl ? t2 : t1).push_back(tiles[k]);
-    }
+    const Groups<GbufDesc> G(descs, tiles, h);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     dhr_status st = DHR_OK;
-    if (!d1.empty()) st = launch_batches<GbufDesc, kGbufMaxB>(ctx, d1, t1, gbuffer_kernel<false>, kBlock, s, what);
-    if (st == DHR_OK && !d2.empty())
-        st = launch_batches<GbufDesc, kGbufMaxB>(ctx, d2, t2, gbuffer_kernel<true>, kBlock, s, what);
+    auto go = [&](Hier k, auto kernel) {
+        if (st == DHR_OK && !G.d[k].empty())
+            st = launch_batches<GbufDesc, kGbufMaxB>(ctx, G.d[k], G.t[k], kernel, kBlock, s, what);
+    };
+    go(kNarrow, gbuffer_kernel<false, false>);
+    go(kWide, gbuffer_kernel<false, true>);
+    go(kTwoLevel, gbuffer_kernel<true, true>);
     return st;
 }
 
@@ -552,23 +583,27 @@ dhr_status frame_jobs(dhr_ctx* ctx, const dhr_gbuffer_job* gj, const dhr_trace_j
                              what, k);
         tiles[k] = tiles_of(gj[k].W, gj[k].H);
     }
+    std::vector<Hier> h(n);
+    for (uint32_t k = 0; k < n; ++k) h[k] = hier_of(ctx, gj[k].bvh);
     DeviceGuard g(ctx->device);
-    std::vector<FrameDesc> d1, d2;
-    std::vector<uint32_t> t1, t2;
-    for (uint32_t k = 0; k < n; ++k) {
-        (descs[k].g.tl ? d2 : d1).push_back(descs[k]);
-        (descs[k].g.tl ? t2 : t1).push_back(tiles[k]);
-    }
+    const Groups<FrameDesc> G(descs, tiles, h);
     unsigned long long* cnt = reinterpret_cast<unsigned long long*>(ctx->trace_counters);
-    if (cnt && !d2.empty())
+    if (cnt && !G.d[kTwoLevel].empty())
         return set_error(ctx, DHR_ERR_UNSUPPORTED, "%s: work counters cover single-level hierarchies only", what);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     dhr_status st = DHR_OK;
-    if (!d1.empty())
-        st = cnt ? launch_batches<FrameDesc, kFrameMaxB>(ctx, d1, t1, frame_kernel<true, false>, kBlock, s, what, cnt)
-                 : launch_batches<FrameDesc, kFrameMaxB>(ctx, d1, t1, frame_kernel<false, false>, kBlock, s, what, cnt);
-    if (st == DHR_OK && !d2.empty())
-        st = launch_batches<FrameDesc, kFrameMaxB>(ctx, d2, t2, frame_kernel<false, true>, kBlock, s, what, cnt);
+    auto go = [&](Hier k, auto kernel) {
+        if (st == DHR_OK && !G.d[k].empty())
+            st = launch_batches<FrameDesc, kFrameMaxB>(ctx, G.d[k], G.t[k], kernel, kBlock, s, what, cnt);
+    };
+    if (cnt) {
+        go(kNarrow, frame_kernel<true, false, false>);
+        go(kWide, frame_kernel<true, false, true>);
+    } else {
+        go(kNarrow, frame_kernel<false, false, false>);
+        go(kWide, frame_kernel<false, false, true>);
+    }
+    go(kTwoLevel, frame_kernel<false, true, true>);
     return st;
 }
 

@@ -9,7 +9,10 @@ oracle; here the fused call is compared with them bit for bit:
 * a batch longer than one launch holds, mixing sizes and hierarchy kinds;
 * its texels against the oracle's on the small scene, as for dhr_gbuffer;
 * mismatched jobs are refused; the counting variant writes the same bytes
-  and counts one primary ray per pixel beyond the visibility rays.
+  and counts one primary ray per pixel beyond the visibility rays;
+* a context whose walks address records by 64-bit offsets (the path of
+  trees beyond 2^26 nodes or triangles, forced by DHR_WIDE_RECORDS=1) writes
+  the same bytes and counts the same work as the 32-bit one.
 """
 import numpy as np
 import pytest
@@ -204,3 +207,47 @@ def test_fused_counting_variant(B, ctx):
     # one primary ray per pixel on top of the visibility rays; primary walks add node visits
     assert cf[0] == ct[0] + W * H
     assert cf[1] > ct[1] and cf[3] >= ct[3]
+
+
+@pytest.fixture(scope="module")
+def wide_ctx(B):
+    import os
+    os.environ["DHR_WIDE_RECORDS"] = "1"
+    try:
+        return B.dhr_create(0)
+    finally:
+        del os.environ["DHR_WIDE_RECORDS"]
+
+
+@pytest.mark.parametrize("preset", ["tiny", "ragged", "room720", "terrain1080"])
+def test_wide_record_addressing_gives_the_same_bytes(B, ctx, wide_ctx, preset):
+    import torch
+    pr = wl.preset(preset)
+    sc, _ = scene(pr.scene)
+    cams = wl.camera_path(pr.camera, 2, sc)
+    lights = wl.lights_for(pr.scene)
+    tp = B.trace_params(pr.W, pr.H, frame=1, seed=pr.seed, n_ao=pr.n_ao, ao_radius=pr.ao_radius,
+                        n_shadow=pr.n_shadow, lights=lights)
+    res, counts = [], []
+    for c in (ctx, wide_ctx):
+        bvh = B.dhr_build_bvh(c, sc.tris, sc.obj_id)
+        a = separate(B, c, bvh, cams[1], cams[0], pr.W, pr.H, tp, len(lights))
+        cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
+        B.dhr_set_trace_counters(c, cnt)
+        try:
+            b = fused(B, c, bvh, cams[1], cams[0], pr.W, pr.H, tp, len(lights))
+        finally:
+            B.dhr_set_trace_counters(c, None)
+        assert_same(a, b, f"{preset}: fused against the two calls")
+        res.append(b)
+        counts.append(cnt.cpu().tolist())
+    if preset == "tiny":
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+        for c in (ctx, wide_ctx):
+            bvh = B.dhr_build_bvh_device(c, dev(np.asarray(sc.tris, np.float32).reshape(-1, 9)),
+                                         dev(np.asarray(sc.obj_id, np.uint32).view(np.int32)))
+            res.append(fused(B, c, bvh, cams[1], cams[0], pr.W, pr.H, tp, len(lights)))
+        assert_same(res[2], res[3], "device-built tree, 32- and 64-bit record offsets")
+    assert_same(res[0], res[1], f"{preset}: 32- and 64-bit record offsets")
+    assert counts[0] == counts[1]
+    print(f"{preset}: 64-bit record offsets give the same texels, counts and work {counts[0]}", flush=True)
