@@ -31,6 +31,14 @@ def flags():
             "-I", os.path.join(HERE, "..", "include")]
 
 
+# Per-source additions.  trace.hip (the BVH walks): the control-flow
+# structurizer leaves regions whose branches are all wave-uniform as they
+# are.  The walk's decisions are ballots and scalar loads; structurised,
+# each of them was carried as a 64-bit lane mask through flag blocks and
+# re-tested, a third of the walk's scalar instructions.
+SOURCE_FLAGS = {"trace.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]}
+
+
 def build(verbose: bool = False, jobs: int = 8) -> str:
     """Compile every source to an object in parallel, then link the library."""
     objdir = os.path.join(HERE, "_build")
@@ -44,7 +52,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         obj = os.path.join(objdir, src + ".o")
         objs.append(obj)
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc()] + flags() + lang + ["-c", path, "-o", obj]
+        cmd = [hipcc()] + flags() + SOURCE_FLAGS.get(src, []) + lang + ["-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))

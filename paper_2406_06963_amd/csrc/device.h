@@ -358,21 +358,38 @@ __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, fl
             const uint64_t m0 = __ballot(t0 <= x0) & __ballot(t0 <= tmax);
             const uint64_t m1 = __ballot(t1 <= x1) & __ballot(t1 <= tmax);
             const bool h0 = COUNT && (t0 <= x0) && (t0 <= tmax), h1 = COUNT && (t1 <= x1) && (t1 <= tmax);
-            if (m0 && m1) {
-                // lanes hitting both children, and those of them nearer child 0
-                const uint64_t both = m0 & m1, f0 = both & __ballot(t0 <= t1);
-                const bool first0 = 2 * __popcll(f0) >= __popcll(both);
-                if (COUNT) {
-                    in_stack = (in_stack & ~(1ull << sp)) | ((first0 ? h1 : h0) ? 1ull << sp : 0ull);
-                    in = first0 ? h0 : h1;
+            // Each branch below tests one scalar comparison made just before
+            // it: booleans combined with others would be kept as lane masks,
+            // at several scalar instructions per node.
+            if ((m0 | m1) != 0) {
+                if (m1 == 0) {
+                    if (COUNT) in = h0;
+                    node = c0;
+                    continue;
                 }
-                wstk[sp++] = first0 ? c1 : c0;
-                node = first0 ? c0 : c1;
-                continue;
-            }
-            if (m0 | m1) {
-                if (COUNT) in = m0 ? h0 : h1;
-                node = m0 ? c0 : c1;
+                if (m0 == 0) {
+                    if (COUNT) in = h1;
+                    node = c1;
+                    continue;
+                }
+                // both children: the nearer one of the majority of the lanes
+                // that hit both goes first
+                const uint64_t both = m0 & m1, f0 = both & __ballot(t0 <= t1);
+                if (2 * __popcll(f0) >= __popcll(both)) {
+                    if (COUNT) {
+                        in_stack = (in_stack & ~(1ull << sp)) | (h1 ? 1ull << sp : 0ull);
+                        in = h0;
+                    }
+                    wstk[sp++] = c1;
+                    node = c0;
+                } else {
+                    if (COUNT) {
+                        in_stack = (in_stack & ~(1ull << sp)) | (h0 ? 1ull << sp : 0ull);
+                        in = h1;
+                    }
+                    wstk[sp++] = c0;
+                    node = c1;
+                }
                 continue;
             }
         } else {
@@ -414,7 +431,7 @@ __device__ __forceinline__ void walk(const float4* __restrict__ nodes, float3 id
 template <bool COUNT, bool WIDE>
 __device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const float4* __restrict__ tris, const Ray& r,
                                         bool live, int* wstk, TravCount* cnt = nullptr) {
-    if (!__any(live)) return false;
+    if (__ballot(live) == 0) return false;
     const float3 id = safe_inv(r.d);
     const float3 ood = f3(r.o.x * id.x, r.o.y * id.y, r.o.z * id.z);
     float tmax = live ? r.tmax : -1.0f;
@@ -423,13 +440,12 @@ __device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const 
     // measured slower on the visibility rays)
     auto leaf = [&](int first, int count) {
         for (int k = 0; k < count; ++k) {
-            if (tri_hits_uniform<WIDE>(tris, first + k, r.o, r.d, tmax)) {  // false for finished lanes (tmax < 0)
-                hit = true;
-                tmax = -1.0f;
-            }
+            const bool h = tri_hits_uniform<WIDE>(tris, first + k, r.o, r.d, tmax);  // false once tmax < 0
+            hit |= h;
+            tmax = h ? -1.0f : tmax;
         }
     };
-    auto done = [&] { return !__any(tmax >= 0.0f); };
+    auto done = [&] { return __ballot(tmax >= 0.0f) == 0; };
     walk<COUNT, WIDE>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt);
     return hit;
 }
@@ -449,11 +465,10 @@ __device__ __forceinline__ int closest_hit(const float4* __restrict__ nodes, con
         leaf_pairs<WIDE>(tris, first, count, [&](const TriRec& rec, int k) {
             const uint32_t orig = fbits(rec.v0.w);
             const float t = tri_t_rec(rec.v0, rec.e1, rec.e2, o, d);
-            if (t > 0.0f && t <= tbest && (t < tbest || orig < best_orig)) {
-                tbest = t;
-                best = k;
-                best_orig = orig;
-            }
+            const bool take = (t > 0.0f) & (t <= tbest) & ((t < tbest) | (orig < best_orig));
+            tbest = take ? t : tbest;
+            best = take ? k : best;
+            best_orig = take ? orig : best_orig;
         });
     };
     auto done = [] { return false; };
@@ -508,12 +523,12 @@ __device__ __forceinline__ void walk_bottom(const float4* __restrict__ nodes, fl
 // is the wave's stack for the bottom levels.
 __device__ __forceinline__ bool any_hit_2l(const float4* __restrict__ top, const TwoLevel& L, const Ray& r, bool live,
                                            int* wstk, int* wstk2) {
-    if (!__any(live)) return false;
+    if (__ballot(live) == 0) return false;
     const float3 id = safe_inv(r.d);
     const float3 ood = f3(r.o.x * id.x, r.o.y * id.y, r.o.z * id.z);
     float tmax = live ? r.tmax : -1.0f;
     bool hit = false;
-    auto done = [&] { return !__any(tmax >= 0.0f); };
+    auto done = [&] { return __ballot(tmax >= 0.0f) == 0; };
     auto top_leaf = [&](int first, int count) {
         for (int k = 0; k < count && !done(); ++k) {
             const float4* I = L.inst + kInstStride * (first + k);
