@@ -352,56 +352,58 @@ __device__ __forceinline__ void packet_walk(const float4* __restrict__ nodes, fl
             box_test<OCT>(load_node_uniform<WIDE>(nodes, node), id, ood, t0, x0, t1, x1, c0, c1);
             c0 = uniform(c0);
             c1 = uniform(c1);
-            // hit masks: entry <= exit and entry <= tmax, each compare's own lane
-            // mask combined on the scalar unit (the distances are never NaN: the
-            // inverse direction is clamped to 1e20)
-            const uint64_t m0 = __ballot(t0 <= x0) & __ballot(t0 <= tmax);
-            const uint64_t m1 = __ballot(t1 <= x1) & __ballot(t1 <= tmax);
+            // hit masks: entry <= min(exit, tmax), one compare per child (the
+            // distances are never NaN: the inverse direction is clamped to 1e20)
+            const uint64_t m0 = __ballot(t0 <= fminf(x0, tmax));
+            const uint64_t m1 = __ballot(t1 <= fminf(x1, tmax));
             const bool h0 = COUNT && (t0 <= x0) && (t0 <= tmax), h1 = COUNT && (t1 <= x1) && (t1 <= tmax);
             // Each branch below tests one scalar comparison made just before
             // it: booleans combined with others would be kept as lane masks,
             // at several scalar instructions per node.
-            if ((m0 | m1) != 0) {
-                if (m1 == 0) {
-                    if (COUNT) in = h0;
-                    node = c0;
-                    continue;
-                }
-                if (m0 == 0) {
-                    if (COUNT) in = h1;
-                    node = c1;
-                    continue;
-                }
-                // both children: the nearer one of the majority of the lanes
-                // that hit both goes first
-                const uint64_t both = m0 & m1, f0 = both & __ballot(t0 <= t1);
-                if (2 * __popcll(f0) >= __popcll(both)) {
-                    if (COUNT) {
-                        in_stack = (in_stack & ~(1ull << sp)) | (h1 ? 1ull << sp : 0ull);
-                        in = h0;
-                    }
-                    wstk[sp++] = c1;
-                    node = c0;
-                } else {
-                    if (COUNT) {
-                        in_stack = (in_stack & ~(1ull << sp)) | (h0 ? 1ull << sp : 0ull);
-                        in = h1;
-                    }
-                    wstk[sp++] = c0;
-                    node = c1;
-                }
+            if ((m0 | m1) == 0) {  // neither child: the next stack entry
+                if (sp == 0) return;
+                node = uniform(wstk[--sp]);
+                if (COUNT) in = (in_stack >> sp) & 1ull;
                 continue;
             }
-        } else {
-            int first, count;
-            leaf_range(node, first, count);
-            if (COUNT && in) {
-                ++cnt->leaves;
-                cnt->tris += count;
+            if (m1 == 0) {
+                if (COUNT) in = h0;
+                node = c0;
+                continue;
             }
-            visit_leaf(first, count);
-            if (done()) return;
+            if (m0 == 0) {
+                if (COUNT) in = h1;
+                node = c1;
+                continue;
+            }
+            // both children: the nearer one of the majority of the lanes that
+            // hit both goes first
+            const uint64_t both = m0 & m1, f0 = both & __ballot(t0 <= t1);
+            if (2 * __popcll(f0) >= __popcll(both)) {
+                if (COUNT) {
+                    in_stack = (in_stack & ~(1ull << sp)) | (h1 ? 1ull << sp : 0ull);
+                    in = h0;
+                }
+                wstk[sp++] = c1;
+                node = c0;
+            } else {
+                if (COUNT) {
+                    in_stack = (in_stack & ~(1ull << sp)) | (h0 ? 1ull << sp : 0ull);
+                    in = h1;
+                }
+                wstk[sp++] = c0;
+                node = c1;
+            }
+            continue;
         }
+        int first, count;
+        leaf_range(node, first, count);
+        if (COUNT && in) {
+            ++cnt->leaves;
+            cnt->tris += count;
+        }
+        visit_leaf(first, count);
+        if (done()) return;
         if (sp == 0) return;
         node = uniform(wstk[--sp]);
         if (COUNT) in = (in_stack >> sp) & 1ull;
