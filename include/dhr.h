@@ -91,7 +91,7 @@ typedef struct {
     uint32_t max_leaf;   /* triangles per leaf, 1..8 (default 4)               */
     uint32_t max_depth;  /* 8..32 (default 32); subtrees switch to median splits
                             so the limit holds (the traversal stack holds 64) */
-    uint32_t sah_bins;   /* binned-SAH bins, 4..64 (default 16)                */
+    uint32_t sah_bins;   /* binned-SAH bins, 4..64 (default 64)                */
     uint32_t threads;    /* host build threads, 0 = hardware concurrency       */
 } dhr_bvh_opts;
 

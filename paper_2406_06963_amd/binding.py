@@ -300,7 +300,7 @@ def dhr_sync(ctx: Context, stream=None):
     _check(ctx, load().dhr_sync(ctx.handle, _stream(stream)), "dhr_sync")
 
 
-def dhr_build_bvh(ctx: Context, tris, obj_id=None, max_leaf=4, max_depth=32, sah_bins=16, threads=0) -> Bvh:
+def dhr_build_bvh(ctx: Context, tris, obj_id=None, max_leaf=4, max_depth=32, sah_bins=64, threads=0) -> Bvh:
     import numpy as np
     t = np.ascontiguousarray(tris, dtype=np.float32).reshape(-1, 9)
     ids = None if obj_id is None else np.ascontiguousarray(obj_id, dtype=np.uint32)
@@ -314,7 +314,7 @@ def dhr_build_bvh(ctx: Context, tris, obj_id=None, max_leaf=4, max_depth=32, sah
 
 
 def dhr_build_bvh_instanced(ctx: Context, base_tris, base_obj, mesh_tris, xforms, inst_obj=None, max_leaf=4,
-                            max_depth=32, sah_bins=16, threads=0) -> Bvh:
+                            max_depth=32, sah_bins=64, threads=0) -> Bvh:
     """Host arrays: base_tris [n,3,3], base_obj [n] or None, mesh_tris [m,3,3],
     xforms [k,3,4] (object to world), inst_obj [k] or None."""
     import numpy as np

@@ -302,7 +302,7 @@ dhr_status dhr_build_bvh(dhr_ctx* ctx, const float* tris, const uint32_t* obj_id
     if (opts) o = *opts;
     if (o.max_leaf == 0) o.max_leaf = 4;
     if (o.max_depth == 0) o.max_depth = 32;
-    if (o.sah_bins == 0) o.sah_bins = 16;
+    if (o.sah_bins == 0) o.sah_bins = 64;
     if (o.max_leaf > 8 || o.max_depth < 8 || o.max_depth > 32 || o.sah_bins < 4 || o.sah_bins > 64)
         return dhr::set_error(ctx, DHR_ERR_INVALID_ARG, "dhr_build_bvh: options out of range");
     if ((uint64_t)(T + o.max_leaf - 1) / o.max_leaf > (1ull << o.max_depth))
@@ -378,7 +378,7 @@ dhr_status dhr_build_bvh_instanced(dhr_ctx* ctx, const float* base_tris, const u
     if (opts) o = *opts;
     if (o.max_leaf == 0) o.max_leaf = 4;
     if (o.max_depth == 0) o.max_depth = 32;
-    if (o.sah_bins == 0) o.sah_bins = 16;
+    if (o.sah_bins == 0) o.sah_bins = 64;
     if (o.max_leaf > 8 || o.max_depth < 8 || o.max_depth > 32 || o.sah_bins < 4 || o.sah_bins > 64)
         return set_error(ctx, DHR_ERR_INVALID_ARG, "%s: options out of range", what);
     for (uint32_t n : {n_base, n_inst + 1})

@@ -116,10 +116,16 @@ struct Ray {
     float tmax;
 };
 
+// Inverse direction for the slab tests, components clamped away from zero
+// (|1/d| <= 1e20).  The hardware reciprocal (about 1 ulp) instead of a
+// correctly rounded division: it only sets where the box tests prune, and
+// the same value serves every plane of a ray, so the test stays monotone in
+// the plane.
 __device__ __forceinline__ float3 safe_inv(float3 d) {
     const float e = 1e-20f;
-    return f3(1.0f / (fabsf(d.x) > e ? d.x : copysignf(e, d.x)), 1.0f / (fabsf(d.y) > e ? d.y : copysignf(e, d.y)),
-              1.0f / (fabsf(d.z) > e ? d.z : copysignf(e, d.z)));
+    return f3(__builtin_amdgcn_rcpf(fabsf(d.x) > e ? d.x : copysignf(e, d.x)),
+              __builtin_amdgcn_rcpf(fabsf(d.y) > e ? d.y : copysignf(e, d.y)),
+              __builtin_amdgcn_rcpf(fabsf(d.z) > e ? d.z : copysignf(e, d.z)));
 }
 
 // A node: the two child boxes (x and y slabs of child 0, of child 1, then the
