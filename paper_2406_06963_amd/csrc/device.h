@@ -257,7 +257,10 @@ __device__ __forceinline__ TriRec load_tri_uniform(const float4* __restrict__ tr
 // Whether the ray hits triangle (v0, e1, e2) at 0 < t < tmax: the
 // Moller-Trumbore tests with the barycentrics and t left unnormalised
 // (multiplied by det, signed by det), so no division is needed.
-__device__ __forceinline__ bool tri_hits_rec(const TriRec& r, float3 o, float3 d, float tmax) {
+struct TriTest {
+    float U, V, T, ad;
+};
+__device__ __forceinline__ TriTest tri_test_rec(const TriRec& r, float3 o, float3 d) {
     const float4 v0 = r.v0, e1 = r.e1, e2 = r.e2;
     const float3 E1 = f3(e1), E2 = f3(e2);
     const float3 p = cross3(d, E2);
@@ -265,11 +268,20 @@ __device__ __forceinline__ bool tri_hits_rec(const TriRec& r, float3 o, float3 d
     const float3 tv = o - f3(v0);
     const float3 q = cross3(tv, E1);
     const uint32_t sgn = fbits(det) & 0x80000000u;
-    const float U = __uint_as_float(fbits(dot3(tv, p)) ^ sgn);
-    const float V = __uint_as_float(fbits(dot3(d, q)) ^ sgn);
-    const float T = __uint_as_float(fbits(dot3(E2, q)) ^ sgn);
-    const float ad = fabsf(det);
-    return (U >= 0.0f) & (V >= 0.0f) & (U + V <= ad) & (T > 0.0f) & (T < tmax * ad);
+    return TriTest{__uint_as_float(fbits(dot3(tv, p)) ^ sgn), __uint_as_float(fbits(dot3(d, q)) ^ sgn),
+                   __uint_as_float(fbits(dot3(E2, q)) ^ sgn), fabsf(det)};
+}
+__device__ __forceinline__ bool tri_hits_rec(const TriRec& r, float3 o, float3 d, float tmax) {
+    const TriTest h = tri_test_rec(r, o, d);
+    return (h.U >= 0.0f) & (h.V >= 0.0f) & (h.U + h.V <= h.ad) & (h.T > 0.0f) & (h.T < tmax * h.ad);
+}
+// The same test for the whole wave as a lane mask, each compare's own
+// ballot combined on the scalar unit (no per-lane flag to materialise).
+__device__ __forceinline__ uint64_t tri_hit_mask(const TriRec& r, float3 o, float3 d, float tmax) {
+    const TriTest h = tri_test_rec(r, o, d);
+    return __builtin_amdgcn_ballot_w64(h.U >= 0.0f) & __builtin_amdgcn_ballot_w64(h.V >= 0.0f) &
+           __builtin_amdgcn_ballot_w64(h.U + h.V <= h.ad) & __builtin_amdgcn_ballot_w64(h.T > 0.0f) &
+           __builtin_amdgcn_ballot_w64(h.T < tmax * h.ad);
 }
 
 template <bool WIDE>
@@ -439,23 +451,25 @@ __device__ __forceinline__ void walk(const float4* __restrict__ nodes, float3 id
 template <bool COUNT, bool WIDE>
 __device__ __forceinline__ bool any_hit(const float4* __restrict__ nodes, const float4* __restrict__ tris, const Ray& r,
                                         bool live, int* wstk, TravCount* cnt = nullptr) {
-    if (__ballot(live) == 0) return false;
+    const uint64_t lives = __ballot(live);
+    if (lives == 0) return false;
     const float3 id = safe_inv(r.d);
     const float3 ood = f3(r.o.x * id.x, r.o.y * id.y, r.o.z * id.z);
     float tmax = live ? r.tmax : -1.0f;
-    bool hit = false;
-    // (one triangle at a time: loading pairs here, as closest_hit does,
-    // measured slower on the visibility rays)
+    // Lanes whose ray has hit, as a wave mask on the scalar unit; a lane's
+    // tmax drops to -1 (it leaves the walk) after the leaf of its hit, so
+    // it may test that leaf's later triangles to no effect.  (One triangle
+    // at a time: loading pairs here, as closest_hit does, measured slower on
+    // the visibility rays.)
+    uint64_t hits = 0;
     auto leaf = [&](int first, int count) {
-        for (int k = 0; k < count; ++k) {
-            const bool h = tri_hits_uniform<WIDE>(tris, first + k, r.o, r.d, tmax);  // false once tmax < 0
-            hit |= h;
-            tmax = h ? -1.0f : tmax;
-        }
+        for (int k = 0; k < count; ++k)
+            hits |= tri_hit_mask(load_tri_uniform<WIDE>(tris, first + k), r.o, r.d, tmax);  // not lanes with tmax < 0
+        tmax = __builtin_amdgcn_inverse_ballot_w64(hits) ? -1.0f : tmax;
     };
-    auto done = [&] { return __ballot(tmax >= 0.0f) == 0; };
+    auto done = [&] { return (lives & ~hits) == 0; };
     walk<COUNT, WIDE>(nodes, id, ood, tmax, live, wstk, leaf, done, cnt);
-    return hit;
+    return __builtin_amdgcn_inverse_ballot_w64(hits);
 }
 
 // Closest hit at t > 0 (ties: lowest original triangle index) for the lanes
