@@ -22,12 +22,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# VALU issue peak in lane operations (slots) per second without packed-FP32
-# instructions (the build disables them): 256 CUs x 4 SIMDs x 16 lanes x
-# 2.4 GHz; an FMA is one slot, a transcendental (exp2, log2, rcp, sqrt) four
-# (quarter rate)
-VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU peak in lane operations (slots) per second: the published FP32 vector
+# rate, 157.3 TFLOP/s with an FMA counted as two flops, is 78.64 T lane-ops/s
+# (256 CUs x 4 SIMDs x 2.4 GHz x 32 lanes: one wave64 instruction per SIMD
+# every two cycles).  An FMA is one slot, a transcendental (exp2, log2, rcp,
+# sqrt) four (quarter rate).
+VALU_PEAK_TSLOTS = 256 * 4 * 32 * 2.4e9 / 1e12
+# An FP32 instruction with an SGPR operand issues at half that rate (measured:
+# 36 T lane-ops/s against 54-66 T for the same FMA with VGPR, inline or
+# literal operands).  The traversal reads node and triangle records into
+# SGPRs, so its slab and triangle arithmetic has that operand by design;
+# each VALU roofline also reports its fraction of this rate.
+VALU_SGPR_TSLOTS = VALU_PEAK_TSLOTS / 2
 SLOT_UNIT = "T VALU lane-ops/s"
+
+
+def valu_roof(ach, **extra):
+    """A VALU roofline object: achieved slots/s against the published peak,
+    with the fraction of the SGPR-operand issue rate beside it."""
+    return {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TSLOTS, "unit": SLOT_UNIT,
+            "frac": ach / VALU_PEAK_TSLOTS if ach else None,
+            "frac_sgpr_operand_rate": ach / VALU_SGPR_TSLOTS if ach else None, **extra}
 # algorithmic VALU slots per unit of work
 SLOTS_PER_NODE = 40      # one node visit: two child slab tests (12 FMA, 12 min/max, entry/exit reductions) and
                          # the hit and order compares
@@ -242,27 +257,23 @@ def main():
     if counts:
         slots = counts[1] * SLOTS_PER_NODE + counts[3] * SLOTS_PER_TRI
         ach = slots / trace_s / 1e12
-        roof_trace = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TSLOTS, "unit": SLOT_UNIT,
-                      "frac": ach / VALU_PEAK_TSLOTS, "traffic": pmc_traffic("trace_kernel"),
-                      "kernel": "trace_kernel (dhr_trace_visibility)", "launch_ms": per["trace"],
-                      "traced_rays": counts[0], "node_visits": counts[1], "leaf_visits": counts[2],
-                      "tri_tests": counts[3], "slots_per_node": SLOTS_PER_NODE, "slots_per_tri": SLOTS_PER_TRI,
-                      "slots_per_launch": slots}
+        roof_trace = valu_roof(ach, traffic=pmc_traffic("trace_kernel"),
+                               kernel="trace_kernel (dhr_trace_visibility)", launch_ms=per["trace"],
+                               traced_rays=counts[0], node_visits=counts[1], leaf_visits=counts[2],
+                               tri_tests=counts[3], slots_per_node=SLOTS_PER_NODE, slots_per_tri=SLOTS_PER_TRI,
+                               slots_per_launch=slots)
     roof_frame = roof_frame_seq = None
     if counts_frame:
         slots = counts_frame[1] * SLOTS_PER_NODE + counts_frame[3] * SLOTS_PER_TRI
         ach = slots / frame_s / 1e12
-        roof_frame = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TSLOTS, "unit": SLOT_UNIT,
-                      "frac": ach / VALU_PEAK_TSLOTS, "traffic": pmc_traffic("frame_kernel"),
-                      "kernel": "frame_kernel (dhr_gbuffer_trace: primary + visibility rays; its timed launches "
-                                "overlap the previous frame's filter)", "launch_ms": per["frame"],
-                      "traced_rays": counts_frame[0], "node_visits": counts_frame[1],
-                      "leaf_visits": counts_frame[2], "tri_tests": counts_frame[3],
-                      "slots_per_node": SLOTS_PER_NODE, "slots_per_tri": SLOTS_PER_TRI, "slots_per_launch": slots}
+        roof_frame = valu_roof(ach, traffic=pmc_traffic("frame_kernel"),
+                               kernel="frame_kernel (dhr_gbuffer_trace: primary + visibility rays; its timed "
+                                      "launches overlap the previous frame's filter)", launch_ms=per["frame"],
+                               traced_rays=counts_frame[0], node_visits=counts_frame[1],
+                               leaf_visits=counts_frame[2], tri_tests=counts_frame[3],
+                               slots_per_node=SLOTS_PER_NODE, slots_per_tri=SLOTS_PER_TRI, slots_per_launch=slots)
         ach_seq = slots / (per["frame_seq"] / 1e3) / 1e12
-        roof_frame_seq = {"bound": "alu", "achieved": ach_seq, "peak": VALU_PEAK_TSLOTS, "unit": SLOT_UNIT,
-                          "frac": ach_seq / VALU_PEAK_TSLOTS, "kernel": "frame_kernel, launched alone",
-                          "launch_ms": per["frame_seq"]}
+        roof_frame_seq = valu_roof(ach_seq, kernel="frame_kernel, launched alone", launch_ms=per["frame_seq"])
     # the dominant kernel: the larger of the two passes run one at a time
     dominant = "frame" if per["frame_seq"] >= per["svgf_seq"] else "svgf"
     roofline = (roof_frame if (dominant == "frame" and roof_frame) else roof_svgf)
@@ -476,8 +487,7 @@ def bench_svgf_levels(B, ctx, W, H, P, g, scratch):
     for l in range(L):
         ms = t[l + 1] - t[l]
         ach = SLOTS_PER_LEVEL_PX * HW / (ms / 1e3) / 1e12 if ms > 0 else None
-        lv.append({"level": l, "ms": ms, "bound": "alu", "unit": SLOT_UNIT, "peak": VALU_PEAK_TSLOTS,
-                   "achieved": ach, "frac": ach / VALU_PEAK_TSLOTS if ach else None,
+        lv.append({"level": l, "ms": ms, **valu_roof(ach),
                    "hbm_frac": 40 * HW / (ms / 1e3) / 1e9 / HBM_PEAK_GBS if ms > 0 else None})
     return {"note": "level l = median of the stack with l + 1 levels minus that with l (one 1080p frame, its "
                     "geometry, synthetic (c, var)); slots per pixel and level: " + str(SLOTS_PER_LEVEL_PX),
@@ -516,10 +526,8 @@ def bench_svgf_batch(B, ctx, bvh, pr, cams, lights, P, f0, n):
     return {"frames": n, "ms": ms, "mpix_s": n * HW / (ms / 1e3) / 1e6,
             "roofline_hbm": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
                              "achieved": nb / (ms / 1e3) / 1e9, "frac": nb / (ms / 1e3) / 1e9 / HBM_PEAK_GBS},
-            "roofline_valu_levels": {"bound": "alu", "unit": SLOT_UNIT, "peak": VALU_PEAK_TSLOTS,
-                                     "achieved": slots / (ms / 1e3) / 1e12,
-                                     "frac": slots / (ms / 1e3) / 1e12 / VALU_PEAK_TSLOTS,
-                                     "note": "the a-trous levels' slots over the whole filter's time"}}
+            "roofline_valu_levels": valu_roof(slots / (ms / 1e3) / 1e12,
+                                              note="the a-trous levels' slots over the whole filter's time")}
 
 
 def bench_light_filter(B, ctx, bvh, pr, cams, lights, gb, ao, sh, P, frames):
@@ -640,9 +648,7 @@ def bench_preset(B, ctx, name, steps, warmup=5):
             "pass_ms": {"frame": t_f, "svgf": t_s, "gbuf": t_g, "trace": t_t},
             "trace_mrays_s": rays / (t_t / 1e3) / 1e6, "svgf_mpix_s": HW / (t_s / 1e3) / 1e6,
             "step_mrays_s": rays / ((t_f + t_s) / 1e3) / 1e6,
-            "roofline_frame": {"bound": "alu", "unit": SLOT_UNIT, "peak": VALU_PEAK_TSLOTS, "achieved": ach,
-                               "frac": ach / VALU_PEAK_TSLOTS, "traced_rays": cnt[0], "node_visits": cnt[1],
-                               "tri_tests": cnt[3]},
+            "roofline_frame": valu_roof(ach, traced_rays=cnt[0], node_visits=cnt[1], tri_tests=cnt[3]),
             "roofline_svgf": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
                               "achieved": svgf_bytes_per_px(pr.levels) * HW / (t_s / 1e3) / 1e9,
                               "frac": svgf_bytes_per_px(pr.levels) * HW / (t_s / 1e3) / 1e9 / HBM_PEAK_GBS}}
@@ -724,9 +730,7 @@ def bench_backward(B, ctx, n_frames):
     bb = px * L * 48
     rf = lambda nb, ms: {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "achieved": nb / (ms / 1e3) / 1e9,
                          "frac": nb / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
-    rv = lambda per_px, ms: {"bound": "alu", "unit": SLOT_UNIT, "peak": VALU_PEAK_TSLOTS,
-                             "slots_per_px_level": per_px, "achieved": per_px * px * L / (ms / 1e3) / 1e12,
-                             "frac": per_px * px * L / (ms / 1e3) / 1e12 / VALU_PEAK_TSLOTS}
+    rv = lambda per_px, ms: valu_roof(per_px * px * L / (ms / 1e3) / 1e12, slots_per_px_level=per_px)
     return {"workload": f"{n_frames} x {W}x{H} room frames, 5 levels, MSE vs 256-spp AO",
             "forward_ms": fw, "backward_ms": bw, "fwd_bwd_ms": fw + bw,
             "fwd_bwd_mpix_s": px / ((fw + bw) / 1e3) / 1e6, "mse": loss0,
