@@ -17,11 +17,25 @@
 namespace dhr {
 namespace {
 
-// waves per workgroup; a workgroup covers an 8 kWaves x 8 pixel tile, one 8 x 8
-// square per wave (each wave's rays come from its own square, so the waves of
-// a workgroup exchange nothing; one and four waves measured slower than two
-// on the 1080p terrain)
-constexpr int kWaves = 2, kTileW = 8 * kWaves, kTileH = 8, kBlock = 64 * kWaves;
+// A workgroup of kWaves waves covers a kTileW x 8 pixel tile.  Its
+// visibility rays come from one 8 x 8 square per wave, squares side by side
+// (a square's hit points keep the union of the wave's paths short).  Its
+// primary rays come from one kPX x kPY rectangle per wave.  Rectangles wider
+// than tall suit primary rays: near a horizon the rows of a square reach
+// very different distances, while a strip's pixels stay at one elevation.
+// The G-buffer texels pass from one layout to the other through LDS, indexed
+// by the pixel's place in the tile.  (One and four waves per workgroup with
+// 8 x 8 primary squares measured slower than two on the 1080p terrain.)
+#ifndef DHR_PRIMARY_W
+#define DHR_PRIMARY_W 16
+#endif
+#ifndef DHR_WAVES
+#define DHR_WAVES 2
+#endif
+constexpr int kWaves = DHR_WAVES, kBlock = 64 * kWaves, kTileW = 8 * kWaves, kTileH = 8;
+constexpr int kPX = DHR_PRIMARY_W, kPY = 64 / kPX, kPWavesX = kTileW / kPX;
+static_assert(kPX * kPY == 64 && kPWavesX >= 1 && kPWavesX * (kTileH / kPY) == kWaves,
+              "primary-ray rectangles must tile the workgroup");
 
 struct LightD {
     uint32_t kind;
@@ -64,10 +78,22 @@ constexpr int kGbufMaxB = 16;
 using GbufBatch = Batch<GbufDesc, kGbufMaxB>;
 static_assert(sizeof(GbufBatch) <= 4000, "kernel arguments too large");
 
-__device__ __forceinline__ void tile_pixel(uint32_t t, uint32_t tiles_x, uint32_t& x, uint32_t& y) {
+// This lane's pixel of tile t in the visibility layout (8 x 8 squares)
+// and in the primary-ray layout (kPX x kPY rectangles); `slot` is the
+// pixel's place in the tile, y kTileW + x.
+__device__ __forceinline__ void vis_pixel(uint32_t t, uint32_t tiles_x, uint32_t& x, uint32_t& y, uint32_t& slot) {
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    x = (t % tiles_x) * kTileW + w * 8 + (lane & 7);
-    y = (t / tiles_x) * kTileH + (lane >> 3);
+    const uint32_t lx = w * 8 + (lane & 7), ly = lane >> 3;
+    x = (t % tiles_x) * kTileW + lx;
+    y = (t / tiles_x) * kTileH + ly;
+    slot = ly * kTileW + lx;
+}
+__device__ __forceinline__ void prim_pixel(uint32_t t, uint32_t tiles_x, uint32_t& x, uint32_t& y, uint32_t& slot) {
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t lx = (w % kPWavesX) * kPX + lane % kPX, ly = (w / kPWavesX) * kPY + lane / kPX;
+    x = (t % tiles_x) * kTileW + lx;
+    y = (t / tiles_x) * kTileH + ly;
+    slot = ly * kTileW + lx;
 }
 
 // Ray `sample` of stream st (0 = AO, l + 1 = light l) of pixel (x, y) with
@@ -135,24 +161,26 @@ struct TraceShared {
     unsigned long long s_bits[kBlock];
 };
 
-// The visibility rays of one 16 x 8 block (tile t of job D) from its
-// G-buffer texels p4, n4 (this lane's pixel (x, y), index i; `inside`
-// false for lanes beyond the image).  Every lane of the workgroup takes
-// part (barriers).  With COUNT, tc and n_rays tally this lane's work.
+// The visibility rays of one kTileW x 8 block (tile t of job D).  This lane
+// brings the G-buffer texel p4, n4 of the pixel at tile slot `ps` (`in_p`
+// false beyond the image) and traces for its pixel (x, y) of the visibility
+// layout (slot vs, index i; `inside` false beyond the image).  Every lane
+// of the workgroup takes part (barriers).  With COUNT, tc and n_rays tally
+// this lane's work.
 template <bool COUNT, bool TWO_LEVEL, bool WIDE>
-__device__ __forceinline__ void trace_block(const TraceDesc& D, uint32_t t, uint32_t x, uint32_t y, bool inside,
-                                            size_t i, float4 p4, float4 n4, TraceShared<TWO_LEVEL>& S, TravCount& tc,
-                                            uint32_t& n_rays) {
+__device__ __forceinline__ void trace_block(const TraceDesc& D, uint32_t t, uint32_t ps, bool in_p, float4 p4,
+                                            float4 n4, uint32_t x, uint32_t y, uint32_t vs, bool inside, size_t i,
+                                            TraceShared<TWO_LEVEL>& S, TravCount& tc, uint32_t& n_rays) {
     const uint32_t tx0 = (t % D.tiles_x) * kTileW, ty0 = (t / D.tiles_x) * kTileH;
     const size_t HW = (size_t)D.W * D.H;
-    const bool valid = inside && n4.w > 0.0f;
+    const bool valid = in_p && n4.w > 0.0f;
     const float3 n = f3(n4);
     const float3 p = f3(p4);
     float eps = D.eps_abs;
     if (!(eps > 0.0f)) eps = fmaxf(1e-3f * D.ao_r, fmaxf(fmaxf(fabsf(p.x), fabsf(p.y)), fabsf(p.z)) * 0x1p-17f);
     const float3 o = p + n * eps;
-    S.s_o[threadIdx.x] = make_float4(o.x, o.y, o.z, valid ? 1.0f : 0.0f);
-    S.s_n[threadIdx.x] = make_float4(n.x, n.y, n.z, 0.0f);
+    S.s_o[ps] = make_float4(o.x, o.y, o.z, valid ? 1.0f : 0.0f);
+    S.s_n[ps] = make_float4(n.x, n.y, n.z, 0.0f);
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int* wstk = S.stack + w * kStack;
@@ -175,11 +203,11 @@ __device__ __forceinline__ void trace_block(const TraceDesc& D, uint32_t t, uint
             // stream covers block b = kWaves (it % P) + w of the tile (8 x 8/P
             // pixels of the wave's own square), P rays of each pixel, counted
             // in LDS.
-            uint32_t src = threadIdx.x, s = it, px = x, py = y;
+            uint32_t src = vs, s = it, px = x, py = y;
             if (P > 1) {
                 const uint32_t b = kWaves * (it % P) + w, q = lane / P;
                 const uint32_t lx = (b % kWaves) * 8 + q % 8, ly = (b / kWaves) * (8 / P) + q / 8;
-                src = (lx / 8) * 64 + ly * 8 + lx % 8;
+                src = ly * kTileW + lx;
                 s = (it / P) * P + lane % P;
                 px = tx0 + lx;
                 py = ty0 + ly;
@@ -205,8 +233,8 @@ __device__ __forceinline__ void trace_block(const TraceDesc& D, uint32_t t, uint
         }
         if (P > 1) {
             __syncthreads();
-            cnt = S.s_cnt[threadIdx.x];
-            bits = S.s_bits[threadIdx.x];
+            cnt = S.s_cnt[vs];
+            bits = S.s_bits[vs];
         }
         if (inside) {
             if (st == 0)
@@ -229,13 +257,13 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const TraceBatch B, unsig
     const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
     const TraceDesc& D = B.d[j];
     const uint32_t t = blockIdx.x - B.tile0[j];
-    uint32_t x, y;
-    tile_pixel(t, D.tiles_x, x, y);
+    uint32_t x, y, vs;
+    vis_pixel(t, D.tiles_x, x, y, vs);
     const bool inside = x < D.W && y < D.H;
     const size_t i = inside ? (size_t)y * D.W + x : 0;
     TravCount tc;
     uint32_t n_rays = 0;
-    trace_block<COUNT, TWO_LEVEL, WIDE>(D, t, x, y, inside, i, D.pos[i], D.nz[i], S, tc, n_rays);
+    trace_block<COUNT, TWO_LEVEL, WIDE>(D, t, vs, inside, D.pos[i], D.nz[i], x, y, vs, inside, i, S, tc, n_rays);
     if (COUNT) {
         // one vector atomic per lane (instrumented runs only)
         atomicAdd(counters + 0, (unsigned long long)n_rays);
@@ -285,8 +313,8 @@ __global__ __launch_bounds__(kBlock) void gbuffer_kernel(const GbufBatch B) {
     __shared__ int stack[kStack * (kBlock / 64) * (TWO_LEVEL ? 2 : 1)];
     const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
     const GbufDesc& D = B.d[j];
-    uint32_t x, y;
-    tile_pixel(blockIdx.x - B.tile0[j], D.tiles_x, x, y);
+    uint32_t x, y, slot;
+    prim_pixel(blockIdx.x - B.tile0[j], D.tiles_x, x, y, slot);
     if (x >= D.W || y >= D.H) return;
     const size_t i = (size_t)y * D.W + x;
     int* wstk = stack + (threadIdx.x >> 6) * kStack;
@@ -295,10 +323,10 @@ __global__ __launch_bounds__(kBlock) void gbuffer_kernel(const GbufBatch B) {
 }
 
 // G-buffer and visibility of a frame in one launch: each workgroup writes the
-// texels of its 16 x 8 block, then traces the block's visibility rays from
-// them (the same block and pixel order as trace_kernel).  The long primary
-// walks of some blocks then overlap other blocks' visibility work instead of
-// leaving the device idle behind them.
+// texels of its kTileW x 8 block (primary-ray layout), then traces the
+// block's visibility rays from them (visibility layout, as trace_kernel).
+// The long primary walks of some blocks then overlap other blocks'
+// visibility work instead of leaving the device idle behind them.
 struct FrameDesc {
     GbufDesc g;
     TraceDesc t;
@@ -315,8 +343,8 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(const FrameBatch B, unsig
     const int j = find_job(B.tile0, (int)B.n, blockIdx.x);
     const FrameDesc& F = B.d[j];
     const uint32_t t = blockIdx.x - B.tile0[j];
-    uint32_t x, y;
-    tile_pixel(t, F.g.tiles_x, x, y);
+    uint32_t x, y, ps;
+    prim_pixel(t, F.g.tiles_x, x, y, ps);
     const bool inside = x < F.g.W && y < F.g.H;
     const size_t i = inside ? (size_t)y * F.g.W + x : 0;
     const uint32_t w = threadIdx.x >> 6;
@@ -333,7 +361,11 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(const FrameBatch B, unsig
         F.g.mv[i] = mv;
     }
     uint32_t n_rays = inside ? 1 : 0;
-    trace_block<COUNT, TWO_LEVEL, WIDE>(F.t, t, x, y, inside, i, pos, nz, S, tc, n_rays);
+    uint32_t vx, vy, vs;
+    vis_pixel(t, F.t.tiles_x, vx, vy, vs);
+    const bool v_in = vx < F.t.W && vy < F.t.H;
+    trace_block<COUNT, TWO_LEVEL, WIDE>(F.t, t, ps, inside, pos, nz, vx, vy, vs, v_in,
+                                        v_in ? (size_t)vy * F.t.W + vx : 0, S, tc, n_rays);
     if (COUNT) {
         atomicAdd(counters + 0, (unsigned long long)n_rays);
         atomicAdd(counters + 1, (unsigned long long)tc.nodes);
