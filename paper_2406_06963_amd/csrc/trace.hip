@@ -151,7 +151,7 @@ __device__ __forceinline__ uint32_t pack_of(uint32_t nr) {
 
 // Workgroup LDS of the visibility pass: the stack columns of its waves (two
 // per wave for two-level hierarchies), and the block's ray origins, normals
-// and per-pixel counts, each indexed by the pixel's slot in the tile.
+// and per-pixel counts.
 template <bool TWO_LEVEL>
 struct TraceShared {
     int stack[kStack * (kBlock / 64) * (TWO_LEVEL ? 2 : 1)];
