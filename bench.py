@@ -111,6 +111,8 @@ def parse():
     ap.add_argument("--bwd-frames", type=int, default=16, help="frames of the differentiation run (0 = skip)")
     ap.add_argument("--other-steps", type=int, default=20,
                     help="timed steps of the 64x64 and 720p workloads (0 = skip)")
+    ap.add_argument("--frames-in-flight", type=int, default=1,
+                    help="G-buffer + visibility launches of later frames run beside a frame's filter")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB three times (a plain copy kernel of "
                          "known size, to calibrate hardware byte counters; 0 = skip)")
@@ -174,7 +176,7 @@ def main():
 
     # frame f + 1's G-buffer + visibility launch overlaps frame f's filter on a
     # second stream, as a renderer (or the serving loop) runs them
-    pipe = FramePipeline(ctx, bvh, W, H, pr.n_ao, len(lights), P, dev)
+    pipe = FramePipeline(ctx, bvh, W, H, pr.n_ao, len(lights), P, dev, frames_in_flight=args.frames_in_flight)
     gb, hist, out, work = pipe.gb, pipe.hist, pipe.out, pipe.work
     ao, sh = pipe.aos[0], pipe.shs[0]          # the single-frame runs below
 
@@ -290,7 +292,7 @@ def main():
                                f"{pr.n_ao} AO ray (r={pr.ao_radius}) + {pr.n_shadow} soft-shadow rays/px, "
                                f"{pr.levels}-level SVGF", "frames": args.steps,
                    "timed_frames": f"{w0}-{w1 - 1} of the camera path (frames 0-{w0 - 1} untimed warmup)",
-                   "parallelism": "single GPU"},
+                   "frames_in_flight": args.frames_in_flight, "parallelism": "single GPU"},
         "trace_mrays_s": rays_per_step / trace_s / 1e6,
         "svgf_mpix_s": HW / svgf_s / 1e6,
         "pass_ms": per,
@@ -583,7 +585,9 @@ def bench_light_filter(B, ctx, bvh, pr, cams, lights, gb, ao, sh, P, frames):
 def bench_preset(B, ctx, name, steps, warmup=5):
     """The same step (G-buffer, rays, SVGF with resident history) on another
     workload: per-pass device time from HIP events, rates of the ray and
-    filter passes."""
+    filter passes, and the step with later frames' rays overlapping a
+    frame's filter (the main workload's schedule, at one and two frames in
+    flight)."""
     import torch
 
     from paper_2406_06963_amd import workloads as wl
@@ -643,11 +647,29 @@ def bench_preset(B, ctx, name, steps, warmup=5):
     cnt = [int(v) / steps for v in c.cpu().tolist()]
     slots = cnt[1] * SLOTS_PER_NODE + cnt[3] * SLOTS_PER_TRI
     ach = slots / (t_f / 1e3) / 1e12
+    # the same frames through the overlapped schedule with one and with two
+    # later frames' rays in flight beside a frame's filter, wall clock
+    # around them
+    from paper_2406_06963_amd.pipeline import FramePipeline
+    tps = [B.trace_params(W, H, frame=f, seed=pr.seed, n_ao=pr.n_ao, ao_radius=pr.ao_radius,
+                          n_shadow=pr.n_shadow, lights=lights) for f in range(warmup + steps)]
+    t_pipe = {}
+    for d in (1, 2):
+        pipe = FramePipeline(ctx, bvh, W, H, pr.n_ao, len(lights), P, frames_in_flight=d)
+        pipe.run(cams, tps, 0, warmup)
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        pipe.run(cams, tps, warmup, warmup + steps)
+        torch.cuda.synchronize()
+        t_pipe[d] = (time.perf_counter() - tp0) * 1e3 / steps
+        del pipe
     return {"workload": f"{name}: {W}x{H}, {pr.scene} scene ({scene.n_tris} tris), {pr.n_ao} AO + {pr.n_shadow} "
                         f"shadow rays/px, {pr.levels}-level SVGF", "steps": steps,
             "pass_ms": {"frame": t_f, "svgf": t_s, "gbuf": t_g, "trace": t_t},
             "trace_mrays_s": rays / (t_t / 1e3) / 1e6, "svgf_mpix_s": HW / (t_s / 1e3) / 1e6,
             "step_mrays_s": rays / ((t_f + t_s) / 1e3) / 1e6,
+            "overlapped_step_ms": {f"{d}_in_flight": t for d, t in t_pipe.items()},
+            "overlapped_step_mrays_s": {f"{d}_in_flight": rays / (t / 1e3) / 1e6 for d, t in t_pipe.items()},
             "roofline_frame": valu_roof(ach, traced_rays=cnt[0], node_visits=cnt[1], tri_tests=cnt[3]),
             "roofline_svgf": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
                               "achieved": svgf_bytes_per_px(pr.levels) * HW / (t_s / 1e3) / 1e9,
