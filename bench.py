@@ -28,21 +28,23 @@ HBM_PEAK_GBS = 8000.0
 # every two cycles).  An FMA is one slot, a transcendental (exp2, log2, rcp,
 # sqrt) four (quarter rate).
 VALU_PEAK_TSLOTS = 256 * 4 * 32 * 2.4e9 / 1e12
-# An FP32 instruction with an SGPR operand issues at half that rate (measured:
-# 36 T lane-ops/s against 54-66 T for the same FMA with VGPR, inline or
-# literal operands).  The traversal reads node and triangle records into
-# SGPRs, so its slab and triangle arithmetic has that operand by design;
-# each VALU roofline also reports its fraction of this rate.
-VALU_SGPR_TSLOTS = VALU_PEAK_TSLOTS / 2
+# Only FP32 FMA, MUL and ADD with VGPR, inline or literal operands issue at
+# that rate (measured: 54-72 T lane-ops/s).  Min, max, max3, compare and
+# select instructions, and any FP32 instruction with an SGPR operand, issue
+# at half of it (measured: 36-43 T).  The traversal's node step is made of
+# those: slab FMAs on node planes held in SGPRs (scalar loads) and the
+# min/max/compare reductions.  Each VALU roofline therefore also reports its
+# fraction of the half rate.
+VALU_HALF_TSLOTS = VALU_PEAK_TSLOTS / 2
 SLOT_UNIT = "T VALU lane-ops/s"
 
 
 def valu_roof(ach, **extra):
     """A VALU roofline object: achieved slots/s against the published peak,
-    with the fraction of the SGPR-operand issue rate beside it."""
+    with the fraction of the half issue rate beside it."""
     return {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TSLOTS, "unit": SLOT_UNIT,
             "frac": ach / VALU_PEAK_TSLOTS if ach else None,
-            "frac_sgpr_operand_rate": ach / VALU_SGPR_TSLOTS if ach else None, **extra}
+            "frac_half_issue_rate": ach / VALU_HALF_TSLOTS if ach else None, **extra}
 # algorithmic VALU slots per unit of work
 SLOTS_PER_NODE = 40      # one node visit: two child slab tests (12 FMA, 12 min/max, entry/exit reductions) and
                          # the hit and order compares
