@@ -44,7 +44,10 @@ def valu_roof(ach, **extra):
     with the fraction of the half issue rate beside it."""
     return {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TSLOTS, "unit": SLOT_UNIT,
             "frac": ach / VALU_PEAK_TSLOTS if ach else None,
-            "frac_half_issue_rate": ach / VALU_HALF_TSLOTS if ach else None, **extra}
+            "frac_half_issue_rate": ach / VALU_HALF_TSLOTS if ach else None,
+            "peak_note": "peak: published FP32 vector rate (157.3 TFLOP/s, FMA = 1 slot), reached by FMA/MUL/ADD "
+                         "on VGPR or constant operands; frac_half_issue_rate: against half of it, the measured "
+                         "rate of min/max/compare/select and of any SGPR-operand instruction", **extra}
 # algorithmic VALU slots per unit of work
 SLOTS_PER_NODE = 40      # one node visit: two child slab tests (12 FMA, 12 min/max, entry/exit reductions) and
                          # the hit and order compares
