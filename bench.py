@@ -44,10 +44,12 @@ def valu_roof(ach, **extra):
     with the fraction of the half issue rate beside it."""
     return {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TSLOTS, "unit": SLOT_UNIT,
             "frac": ach / VALU_PEAK_TSLOTS if ach else None,
-            "frac_half_issue_rate": ach / VALU_HALF_TSLOTS if ach else None,
-            "peak_note": "peak: published FP32 vector rate (157.3 TFLOP/s, FMA = 1 slot), reached by FMA/MUL/ADD "
-                         "on VGPR or constant operands; frac_half_issue_rate: against half of it, the measured "
-                         "rate of min/max/compare/select and of any SGPR-operand instruction", **extra}
+            "frac_half_issue_rate": ach / VALU_HALF_TSLOTS if ach else None, **extra}
+
+
+PEAK_NOTE = ("peak: the published FP32 vector rate (157.3 TFLOP/s, an FMA = 1 slot), reached by FMA/MUL/ADD on VGPR "
+             "or constant operands; frac_half_issue_rate: against half of it, the measured issue rate of "
+             "min/max/compare/select and of any instruction with an SGPR operand (the walk's whole mix)")
 # algorithmic VALU slots per unit of work
 SLOTS_PER_NODE = 40      # one node visit: two child slab tests (12 FMA, 12 min/max, entry/exit reductions) and
                          # the hit and order compares
@@ -273,7 +275,7 @@ def main():
     if counts_frame:
         slots = counts_frame[1] * SLOTS_PER_NODE + counts_frame[3] * SLOTS_PER_TRI
         ach = slots / frame_s / 1e12
-        roof_frame = valu_roof(ach, traffic=pmc_traffic("frame_kernel"),
+        roof_frame = valu_roof(ach, traffic=pmc_traffic("frame_kernel"), peak_note=PEAK_NOTE,
                                kernel="frame_kernel (dhr_gbuffer_trace: primary + visibility rays; its timed "
                                       "launches overlap the previous frame's filter)", launch_ms=per["frame"],
                                traced_rays=counts_frame[0], node_visits=counts_frame[1],
